@@ -1,0 +1,322 @@
+"""Plain FP64 CPU oracle for the probabilistic VLBM Mach-2000 jet ensemble.
+
+TEST INFRASTRUCTURE.  Only ``tests/``, ``__graft_entry__.smoke()`` and the
+``cpu_baseline`` leg of ``bench.py`` may import this package.  It shares no
+code with the HIP library (``paper_2605_25282_amd``) and never imports it.
+
+The stepping arithmetic lives in ``vlbm_oracle.c`` (one realization at a time,
+one node at a time, FP64, no fast-math).  The ensemble statistics of Sec. 3.2
+and Sec. 3.4 of the paper (restriction, mean, population standard deviation,
+one-point Wasserstein-1) are written below with numpy, each one the plain
+definition it cites.
+
+State layout used by this package for one realization: a float64 array of
+shape (20, ny, nx); row ``s*4 + v`` is variable v (rho, rho v1, rho v2, E) of
+slot s (0 = macroscopic u, 1..4 = populations u_1..u_4).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from concurrent.futures import ThreadPoolExecutor
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "vlbm_oracle.c")
+_LIB = os.path.join(_HERE, "libvlbm_oracle.so")
+
+BC = {"jet": 0, "periodic": 1, "neumann": 2}
+THETA = {"limiter": 0, "zero": 1, "one": 2, "given": 3}
+OK, ERR_ARG, ERR_NONPOSITIVE, ERR_NONFINITE = 0, -1, -4, -5
+
+
+def build(force: bool = True) -> str:
+    """Compile vlbm_oracle.c with gcc (FP64, contraction off, no fast-math)."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp"
+        subprocess.run(
+            ["gcc", "-O2", "-std=gnu99", "-ffp-contract=off", "-fno-fast-math", "-fPIC",
+             "-shared", _SRC, "-o", tmp, "-lquadmath", "-lm"],
+            check=True)
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+class _Params(ctypes.Structure):
+    _fields_ = [("gamma", ctypes.c_double), ("alpha", ctypes.c_double),
+                ("kappa", ctypes.c_double), ("rlmp_relax", ctypes.c_double),
+                ("pos_eps", ctypes.c_double), ("rho_amb", ctypes.c_double),
+                ("p_amb", ctypes.c_double), ("rho_jet", ctypes.c_double),
+                ("v_jet", ctypes.c_double), ("r_jet", ctypes.c_double),
+                ("kl_amp", ctypes.c_double), ("kl_modes", ctypes.c_int32),
+                ("kl_decay", ctypes.c_int32), ("bc", ctypes.c_int32),
+                ("theta_mode", ctypes.c_int32)]
+
+
+class _Grid(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32),
+                ("dx", ctypes.c_double), ("y_min", ctypes.c_double)]
+
+
+@dataclass
+class Params:
+    """Physical and numerical parameters (Sec. 2.1-2.3 of the paper)."""
+    gamma: float = 5.0 / 3.0
+    alpha: float = 0.0
+    kappa: float = 1.0
+    rlmp_relax: float = 0.1
+    pos_eps: float = 1e-2
+    rho_amb: float = 0.5
+    p_amb: float = 0.4127
+    rho_jet: float = 5.0
+    v_jet: float = 800.0
+    r_jet: float = 0.05
+    kl_amp: float = 0.1
+    kl_decay: int = 2
+    kl_modes: int = 10
+    bc: str = "jet"
+    theta_mode: str = "limiter"
+
+    def c(self) -> _Params:
+        return _Params(self.gamma, self.alpha, self.kappa, self.rlmp_relax, self.pos_eps,
+                       self.rho_amb, self.p_amb, self.rho_jet, self.v_jet, self.r_jet,
+                       self.kl_amp, self.kl_modes, self.kl_decay, BC[self.bc],
+                       THETA[self.theta_mode])
+
+
+@dataclass
+class Grid:
+    """Cell-centred uniform grid: node (i, j) at x = (i+1/2) dx, y = y_min + (j+1/2) dx."""
+    nx: int
+    ny: int
+    dx: float
+    y_min: float = 0.0
+
+    def c(self) -> _Grid:
+        return _Grid(self.nx, self.ny, self.dx, self.y_min)
+
+    def y(self) -> np.ndarray:
+        return self.y_min + (np.arange(self.ny) + 0.5) * self.dx
+
+
+_lib_handle = None
+_dp = ctypes.POINTER(ctypes.c_double)
+
+
+def _lib():
+    global _lib_handle
+    if _lib_handle is None:
+        path = _LIB if os.path.exists(_LIB) else build(force=False)
+        lib = ctypes.CDLL(path)
+        P, G = ctypes.POINTER(_Params), ctypes.POINTER(_Grid)
+        lib.orc_pressure.argtypes = [P, _dp]
+        lib.orc_pressure.restype = ctypes.c_double
+        lib.orc_fluxes.argtypes = [P, _dp, _dp, _dp]
+        lib.orc_maxwellians.argtypes = [P, ctypes.c_double, _dp, _dp]
+        lib.orc_wave_speed.argtypes = [P, _dp, ctypes.POINTER(ctypes.c_int)]
+        lib.orc_wave_speed.restype = ctypes.c_double
+        lib.orc_inlet_density.argtypes = [P, ctypes.c_double, _dp]
+        lib.orc_inlet_density.restype = ctypes.c_double
+        lib.orc_inlet_state.argtypes = [P, ctypes.c_double, _dp, _dp]
+        lib.orc_kinetic_speed.argtypes = [P, G, _dp]
+        lib.orc_kinetic_speed.restype = ctypes.c_double
+        lib.orc_fill_equilibrium.argtypes = [P, G, ctypes.c_double, _dp]
+        lib.orc_init.argtypes = [P, G, _dp, _dp]
+        lib.orc_init.restype = ctypes.c_int
+        lib.orc_side_theta.argtypes = [P, _dp, ctypes.c_double, ctypes.c_double,
+                                       ctypes.c_double, _dp]
+        lib.orc_side_theta.restype = ctypes.c_double
+        lib.orc_step.argtypes = [P, G, ctypes.c_double, _dp, _dp, _dp, _dp, _dp, _dp, _dp]
+        lib.orc_step.restype = ctypes.c_int
+        lib.orc_run.argtypes = [P, G, ctypes.c_double, ctypes.c_int64, _dp,
+                                ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64),
+                                ctypes.POINTER(ctypes.c_double)]
+        lib.orc_run.restype = ctypes.c_int
+        _lib_handle = lib
+    return _lib_handle
+
+
+def _ptr(a: np.ndarray | None):
+    if a is None:
+        return None
+    assert a.dtype == np.float64 and a.flags.c_contiguous
+    return a.ctypes.data_as(_dp)
+
+
+def _vec(x) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(x, dtype=np.float64))
+
+
+# --------------------------------------------------------------------------
+# Pointwise physics (eq:eos, eq:fluxF, eq:fluxG, eq:maxwellians12-5)
+# --------------------------------------------------------------------------
+
+def pressure(p: Params, u) -> float:
+    return _lib().orc_pressure(ctypes.byref(p.c()), _ptr(_vec(u)))
+
+
+def fluxes(p: Params, u):
+    f, g = np.zeros(4), np.zeros(4)
+    _lib().orc_fluxes(ctypes.byref(p.c()), _ptr(_vec(u)), _ptr(f), _ptr(g))
+    return f, g
+
+
+def maxwellians(p: Params, a: float, u) -> np.ndarray:
+    """Return M[k][v], k = 0..3 for M_1..M_4."""
+    M = np.zeros(16)
+    _lib().orc_maxwellians(ctypes.byref(p.c()), a, _ptr(_vec(u)), _ptr(M))
+    return M.reshape(4, 4)
+
+
+def wave_speed(p: Params, u) -> tuple[float, bool]:
+    bad = ctypes.c_int(0)
+    s = _lib().orc_wave_speed(ctypes.byref(p.c()), _ptr(_vec(u)), ctypes.byref(bad))
+    return s, bool(bad.value)
+
+
+def inlet_density(p: Params, y: float, coef) -> float:
+    return _lib().orc_inlet_density(ctypes.byref(p.c()), float(y), _ptr(_vec(coef)))
+
+
+def inlet_state(p: Params, y: float, coef) -> np.ndarray:
+    u = np.zeros(4)
+    _lib().orc_inlet_state(ctypes.byref(p.c()), float(y), _ptr(_vec(coef)), _ptr(u))
+    return u
+
+
+def side_theta(p: Params, L, rmin, rmax, rhoeL, D) -> float:
+    return _lib().orc_side_theta(ctypes.byref(p.c()), _ptr(_vec(L)), rmin, rmax, rhoeL,
+                                 _ptr(_vec(D)))
+
+
+# --------------------------------------------------------------------------
+# Whole-grid operations on one realization
+# --------------------------------------------------------------------------
+
+def init(p: Params, g: Grid, coef) -> np.ndarray:
+    """Initial datum of eq:u0_def with equilibrium populations."""
+    st = np.zeros((20, g.ny, g.nx))
+    rc = _lib().orc_init(ctypes.byref(p.c()), ctypes.byref(g.c()), _ptr(_vec(coef)), _ptr(st))
+    if rc != OK:
+        raise RuntimeError(f"orc_init failed: {rc}")
+    return st
+
+
+def kinetic_speed(p: Params, g: Grid, st: np.ndarray) -> float:
+    return _lib().orc_kinetic_speed(ctypes.byref(p.c()), ctypes.byref(g.c()), _ptr(st))
+
+
+def fill_equilibrium(p: Params, g: Grid, a: float, st: np.ndarray) -> None:
+    _lib().orc_fill_equilibrium(ctypes.byref(p.c()), ctypes.byref(g.c()), a, _ptr(st))
+
+
+def from_macroscopic(p: Params, g: Grid, u: np.ndarray) -> np.ndarray:
+    """State with macroscopic field u (4, ny, nx) and equilibrium populations."""
+    st = np.zeros((20, g.ny, g.nx))
+    st[0:4] = u
+    a = kinetic_speed(p, g, st)
+    if not a > 0:
+        raise ValueError("state not admissible")
+    fill_equilibrium(p, g, a, st)
+    return st
+
+
+def step(p: Params, g: Grid, a: float, st: np.ndarray, theta_x=None, theta_y=None,
+         diagnostics: bool = False):
+    """One stream-collide step (eq:vlbm1-eq:vlbm5) with kinetic speed a.
+
+    Returns (new_state, status) or, with diagnostics, (new_state, status,
+    theta_x, theta_y, bounds) where bounds = (rho_min', rho_max', rho e_L)."""
+    new = np.zeros_like(st)
+    tx_in = None if theta_x is None else _vec(theta_x)
+    ty_in = None if theta_y is None else _vec(theta_y)
+    tx = np.zeros((g.ny, g.nx)) if diagnostics else None
+    ty = np.zeros((g.ny, g.nx)) if diagnostics else None
+    bd = np.zeros((3, g.ny, g.nx)) if diagnostics else None
+    rc = _lib().orc_step(ctypes.byref(p.c()), ctypes.byref(g.c()), a, _ptr(st), _ptr(new),
+                         _ptr(tx_in), _ptr(ty_in), _ptr(tx), _ptr(ty), _ptr(bd))
+    if rc == ERR_ARG:
+        raise ValueError("orc_step: bad arguments")
+    if diagnostics:
+        return new, rc, tx, ty, bd
+    return new, rc
+
+
+def run(p: Params, g: Grid, st: np.ndarray, t_final: float, max_steps: int = 1 << 40,
+        t: float = 0.0):
+    """Time loop of Sec. 2.3 (dt = dx / a_n).  Returns (state, t, steps, a_last, status)."""
+    st = np.ascontiguousarray(st.copy())
+    tt, ss, al = ctypes.c_double(t), ctypes.c_int64(0), ctypes.c_double(0.0)
+    rc = _lib().orc_run(ctypes.byref(p.c()), ctypes.byref(g.c()), t_final, int(max_steps),
+                        _ptr(st), ctypes.byref(tt), ctypes.byref(ss), ctypes.byref(al))
+    return st, tt.value, ss.value, al.value, rc
+
+
+def run_ensemble(p: Params, g: Grid, coefs: np.ndarray, t_final: float,
+                 max_steps: int = 1 << 40, threads: int | None = None):
+    """Independent realizations (one per row of coefs), each from eq:u0_def.
+
+    The C loop releases the GIL, so realizations run concurrently on
+    ``threads`` host threads.  Returns (states [M,20,ny,nx], t [M], steps [M],
+    status [M])."""
+    coefs = np.asarray(coefs, dtype=np.float64)
+    M = coefs.shape[0]
+    threads = threads or min(M, os.cpu_count() or 1)
+
+    def one(m):
+        st0 = init(p, g, coefs[m])
+        return run(p, g, st0, t_final, max_steps)
+
+    with ThreadPoolExecutor(max_workers=threads) as ex:
+        res = list(ex.map(one, range(M)))
+    states = np.stack([r[0] for r in res])
+    return (states, np.array([r[1] for r in res]), np.array([r[2] for r in res]),
+            np.array([r[4] for r in res]))
+
+
+# --------------------------------------------------------------------------
+# Ensemble statistics (Sec. 3.2 restriction, Sec. 3.4 observables)
+# --------------------------------------------------------------------------
+
+def moments(p: Params, u: np.ndarray):
+    """Density, speed |v| and pressure (eq:eos) of macroscopic fields u[..., 4 vars, ny, nx]
+    given as the leading 4 rows of the last three axes."""
+    rho, m1, m2, E = u[..., 0, :, :], u[..., 1, :, :], u[..., 2, :, :], u[..., 3, :, :]
+    v1 = m1 / rho
+    v2 = m2 / rho
+    pr = (p.gamma - 1.0) * (E - 0.5 * rho * (v1 * v1 + v2 * v2))
+    speed = np.sqrt(v1 * v1 + v2 * v2)
+    return rho, speed, pr
+
+
+def restrict(field: np.ndarray, r: int) -> np.ndarray:
+    """Conservative restriction of Sec. 3.2: each coarse cell is the average of
+    the r x r fine nodes it contains (last two axes are y, x)."""
+    *lead, ny, nx = field.shape
+    if ny % r or nx % r:
+        raise ValueError("grid not divisible by the restriction factor")
+    blocks = field.reshape(*lead, ny // r, r, nx // r, r)
+    return blocks.sum(axis=(-3, -1)) / (r * r)
+
+
+def ensemble_mean(samples: np.ndarray) -> np.ndarray:
+    """E_M of eq:mean: (1/M) sum over the realization axis 0."""
+    return samples.sum(axis=0) / samples.shape[0]
+
+
+def ensemble_std(samples: np.ndarray) -> np.ndarray:
+    """Square root of the population variance used in eq:std (divide by M)."""
+    mean = ensemble_mean(samples)
+    return np.sqrt(((samples - mean) ** 2).sum(axis=0) / samples.shape[0])
+
+
+def w1(a: np.ndarray, b: np.ndarray) -> np.ndarray:
+    """Per-cell one-point Wasserstein-1 of eq:w1disc between two equal-size
+    empirical laws (realization axis 0): mean absolute difference of the
+    ascending order statistics."""
+    if a.shape != b.shape:
+        raise ValueError("equal ensemble sizes and grids required")
+    return np.abs(np.sort(a, axis=0) - np.sort(b, axis=0)).sum(axis=0) / a.shape[0]
