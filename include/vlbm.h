@@ -1,0 +1,224 @@
+/*
+ * vlbm.h -- C ABI of the MI355X (gfx950) library for ensembles of the
+ * vectorial lattice Boltzmann method (VLBM, D2Q5) applied to the Mach-2000
+ * jet of Simonis & Wissocq, "Computing statistical solutions of a Mach 2000
+ * astrophysical jet".
+ *
+ * The library advances many Monte Carlo realizations of the random
+ * initial-boundary-value problem (eq:ibvp, Sec. 2.2) with the blended
+ * stream-collide scheme of eq:vlbm1-eq:vlbm5 (Sec. 2.1), time step
+ * dt = dx / a_n with the kinetic speed re-evaluated every step (Sec. 2.3),
+ * and computes the ensemble statistics of Sec. 3 on the device: conservative
+ * restriction (Sec. 3.2), per-cell mean (eq:mean), population standard
+ * deviation (eq:std) and the one-point Wasserstein-1 distance from sorted
+ * samples (eq:w1disc).
+ *
+ * Conventions for every entry point:
+ *   - The return value is a vlbm_status: VLBM_OK (0) or a negative code.
+ *     vlbm_last_error() returns a message for the calling thread's last
+ *     failure.  No C++ exception crosses this interface.
+ *   - All arguments are validated before anything is enqueued; a call that
+ *     returns VLBM_ERR_ARG or VLBM_ERR_SIZE has enqueued nothing.
+ *   - The caller owns all state, sample and statistics memory (device
+ *     pointers, e.g. from torch.empty(..., device="cuda")) and keeps it alive
+ *     until vlbm_destroy().  The library allocates only small per-ensemble
+ *     control arrays (a few doubles per realization) and frees them in
+ *     vlbm_destroy().
+ *   - Work is enqueued on the HIP stream given at creation (hip_stream;
+ *     NULL = the null stream) and is asynchronous, except where a call says
+ *     it synchronizes.
+ *   - Device-side failures (a non-positive density or internal energy, a
+ *     non-finite value) are latched per realization and reported by the next
+ *     synchronizing call (vlbm_step with all_done != NULL, vlbm_times).
+ *
+ * State layout of one mesh level (FP64 precision), in one state buffer:
+ *     double st[4 var][5 slot][R realizations][ny][nx]
+ * var = (rho, rho v1, rho v2, E); slot 0 is the macroscopic state u, slots
+ * 1..4 are the populations u_1..u_4 (u_5 is eliminated, Sec. 2.1).  Node
+ * (i, j) sits at x = (i + 1/2) dx, y = y_min + (j + 1/2) dx.  Two buffers of
+ * vlbm_state_bytes() each are needed per level; which one holds a given
+ * realization's current state depends on its step count, so read states only
+ * through vlbm_get_state, vlbm_moments or vlbm_ensemble_stats.
+ * With VLBM_MIXED the rho, rho v1, rho v2 planes (all 5 slots) are stored
+ * as FP32 first, followed by the E planes in FP64; all arithmetic is FP64.
+ */
+#ifndef VLBM_H
+#define VLBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t vlbm_status;
+
+#define VLBM_OK 0
+#define VLBM_ERR_ARG (-1)         /* invalid argument                          */
+#define VLBM_ERR_HIP (-2)         /* HIP runtime error                         */
+#define VLBM_ERR_SIZE (-3)        /* size outside the supported range          */
+#define VLBM_ERR_NONPOSITIVE (-4) /* a realization produced rho <= 0 or rho e <= 0 */
+#define VLBM_ERR_NONFINITE (-5)   /* a realization produced a non-finite value  */
+#define VLBM_ERR_STATE (-6)       /* call not valid in the handle's state       */
+
+/* Boundary treatment (Sec. 2.2). */
+#define VLBM_BC_JET 0      /* column 0: Dirichlet inlet (eq:inletBC); last column and
+                              first/last rows: zero-gradient copy layers
+                              (eq:outletBC, eq:transverseBC)                       */
+#define VLBM_BC_PERIODIC 1 /* periodic in x and y (verification problems)         */
+#define VLBM_BC_NEUMANN 2  /* zero-gradient copy layers on all four sides         */
+
+/* Blending parameter theta of eq:vlbm1-eq:vlbm5. */
+#define VLBM_LIMITER_RLMP 0 /* per-face limiter: relaxed local density bounds and
+                               an internal-energy floor                             */
+#define VLBM_THETA_ZERO 1   /* first-order update                                   */
+#define VLBM_THETA_ONE 2    /* unlimited second-order update                        */
+
+/* Storage precision of the state. */
+#define VLBM_FP64 0
+#define VLBM_MIXED 1 /* rho and rho v planes FP32, E planes FP64 */
+
+typedef struct vlbm_params {
+    double gamma;      /* heat-capacity ratio, eq:eos (5/3)                       */
+    double alpha;      /* rest-population weight of eq:maxwellians5, in [0, 1)    */
+    double kappa;      /* safety factor >= 1 on the Bouchut kinetic speed         */
+    double rlmp_relax; /* relaxation of the local density bounds (>= 0)          */
+    double pos_eps;    /* internal-energy floor, fraction of the low-order value  */
+    double rho_amb;    /* ambient density (0.5), Sec. 2.2                         */
+    double p_amb;      /* ambient pressure (0.4127)                               */
+    double rho_jet;    /* mean jet density (5)                                    */
+    double v_jet;      /* jet velocity (800)                                      */
+    double r_jet;      /* jet radius (0.05)                                       */
+    double kl_amp;     /* amplitude A of eq:karhunenExp (0.1)                     */
+    int32_t kl_modes;  /* K of eq:karhunenExp (10), 0 <= K <= 64                  */
+    int32_t kl_decay;  /* integer decay exponent p of eq:karhunenExp (2), 0..16   */
+    int32_t bc;        /* VLBM_BC_*                                              */
+    int32_t limiter;   /* VLBM_LIMITER_RLMP or VLBM_THETA_*                      */
+    int32_t precision; /* VLBM_FP64 or VLBM_MIXED                                */
+    int32_t reserved;  /* must be 0                                              */
+} vlbm_params;
+
+typedef struct vlbm_level {
+    int32_t nx, ny;  /* nodes including boundary layers, each >= 3 (>= 1 periodic) */
+    double dx;       /* mesh width (square cells), > 0                            */
+    double y_min;    /* lower domain edge                                         */
+    void *state[2];  /* two device buffers of vlbm_state_bytes() bytes each,      */
+                     /* 256-byte aligned                                          */
+} vlbm_level;
+
+typedef struct vlbm_ensemble vlbm_ensemble;
+
+/* Message for the calling thread's last failed call (never NULL). */
+const char *vlbm_last_error(void);
+
+/* Bytes of ONE state buffer for R realizations of an nx x ny level. */
+vlbm_status vlbm_state_bytes(const vlbm_params *p, int32_t nx, int32_t ny, int32_t n_real,
+                             size_t *bytes);
+
+/*
+ * Create an ensemble of n_real realizations on each of n_levels mesh levels
+ * and enqueue its initial datum (eq:u0_def, Sec. 2.2; populations at
+ * equilibrium with the initial kinetic speed).
+ *   coeffs: HOST array [n_real][2 * kl_modes]; row m holds the coefficients
+ *           Y_1, Z_1, Y_2, Z_2, ... in [-1, 1] of eq:karhunenExp for
+ *           realization m (the random draw omega_m of Sec. 2.3).  The same
+ *           rows are used on every level.  Copied before the call returns.
+ *           May be NULL when bc != VLBM_BC_JET.
+ *   For bc != VLBM_BC_JET the initial state is ambient everywhere; use
+ *   vlbm_set_macroscopic afterwards to load another initial state.
+ *   hip_stream: the hipStream_t all work of this ensemble is enqueued on.
+ * On success *out receives the handle; destroy it with vlbm_destroy.
+ */
+vlbm_status vlbm_init_ensemble(const vlbm_params *p, const vlbm_level *levels, int32_t n_levels,
+                               const double *coeffs, int32_t n_real, void *hip_stream,
+                               vlbm_ensemble **out);
+
+/*
+ * Replace the state of one level by the macroscopic field u (DEVICE,
+ * double [4 var][n_real][ny][nx]) with populations at equilibrium for the
+ * kinetic speed of u, and reset time and step counters of that level to 0.
+ */
+vlbm_status vlbm_set_macroscopic(vlbm_ensemble *e, int32_t level, const double *u);
+
+/*
+ * Advance every realization of every level by up to n_steps steps of
+ * eq:vlbm1-eq:vlbm5, each realization stopping exactly at t_final (the last
+ * steps are shortened, taking a = dx/dt).  Realizations already at t_final
+ * are left untouched.  If all_done is non-NULL the call synchronizes the
+ * stream, sets *all_done to 1 when every realization has reached t_final
+ * (else 0), and returns VLBM_ERR_NONPOSITIVE / VLBM_ERR_NONFINITE if any
+ * realization has latched a failure.
+ */
+vlbm_status vlbm_step(vlbm_ensemble *e, double t_final, int32_t n_steps, int32_t *all_done);
+
+/*
+ * Per-realization time, step count, kinetic speed of the last step and
+ * latched status (0, VLBM_ERR_NONPOSITIVE or VLBM_ERR_NONFINITE) of one
+ * level, into HOST arrays of n_real entries (each may be NULL).  Synchronizes.
+ */
+vlbm_status vlbm_times(const vlbm_ensemble *e, int32_t level, double *t, int64_t *steps,
+                       double *a_last, int32_t *status);
+
+/*
+ * Copy the current state of one level into the DEVICE buffer out, FP64,
+ * layout [4 var][5 slot][n_real][ny][nx] (checkpointing, inspection).
+ */
+vlbm_status vlbm_get_state(const vlbm_ensemble *e, int32_t level, double *out);
+
+/*
+ * Macroscopic moments of the current state of one level: density, speed
+ * |v| and pressure p (eq:eos), DEVICE arrays [n_real][ny][nx] (each may be
+ * NULL).
+ */
+vlbm_status vlbm_moments(const vlbm_ensemble *e, int32_t level, double *rho, double *speed,
+                         double *p);
+
+/*
+ * Ensemble statistics of one level, for batches of realizations (Sec. 3).
+ * Every realization's density, speed and pressure are restricted to the
+ * coarse grid by r x r block averaging (Sec. 3.2; r >= 1 divides nx and ny;
+ * n_cells = (ny/r)(nx/r)), then merged into the running accumulator acc:
+ *   acc: DEVICE double [3 field][2][n_cells]: per field (rho, |v|, p) the
+ *        running mean and the sum of squared deviations M2 of the
+ *        n_prev realizations merged so far (contents ignored when n_prev = 0).
+ *        Batches are merged with the pairwise update of Chan, Golub & LeVeque.
+ *   samples: DEVICE double [m_total][n_cells] or NULL; receives the restricted
+ *        density of realization m in row m_offset + m (input of the one-point
+ *        Wasserstein distance).  The caller guarantees m_offset + n_real <= m_total.
+ */
+vlbm_status vlbm_ensemble_stats(const vlbm_ensemble *e, int32_t level, int32_t r, double *acc,
+                                int64_t n_prev, double *samples, int64_t m_offset);
+
+/*
+ * Mean and population standard deviation (eq:mean, eq:std: sqrt(M2 / n))
+ * from an accumulator of n_total realizations: DEVICE double [3][n_cells]
+ * each (either may be NULL).  Enqueued on hip_stream.
+ */
+vlbm_status vlbm_stats_finalize(const double *acc, int64_t n_cells, int64_t n_total,
+                                double *mean, double *std, void *hip_stream);
+
+/*
+ * Sort, in place and ascending, the m samples of every cell of a sample
+ * store DEVICE double [m][n_cells] (the order statistics of eq:w1disc).
+ * 1 <= m <= 4096.  Enqueued on hip_stream.
+ */
+vlbm_status vlbm_sort_samples(double *samples, int64_t n_cells, int32_t m, void *hip_stream);
+
+/*
+ * One-point Wasserstein-1 distance (eq:w1disc) between two sorted sample
+ * stores of equal size [m][n_cells]: w1_cell[k] = (1/m) sum_m |a_(m) - b_(m)|
+ * (DEVICE [n_cells] or NULL) and its average over cells (DEVICE scalar or
+ * NULL).  Enqueued on hip_stream.
+ */
+vlbm_status vlbm_w1(const double *sorted_a, const double *sorted_b, int64_t n_cells, int32_t m,
+                    double *w1_cell, double *w1_mean, void *hip_stream);
+
+/* Release the handle and its control arrays (synchronizes its stream). */
+vlbm_status vlbm_destroy(vlbm_ensemble *e);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* VLBM_H */

@@ -1,0 +1,532 @@
+// vlbm_api.hip -- host side of the C ABI declared in include/vlbm.h.
+//
+// The host validates every argument before enqueueing anything, owns the
+// per-ensemble control ring (time, step count, kinetic speed, wave-speed
+// maximum, latched status per realization) and sequences the kernels of
+// vlbm_kernels.hip on the caller's stream.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/vlbm.h"
+#include "vlbm_device.h"
+
+namespace vlbm {
+template <int PREC> __global__ void init_macro_kernel(PhysArgs, LevelArgs, const double *, Ctl);
+template <int PREC> __global__ void equilibrium_kernel(PhysArgs, LevelArgs, Ctl, int);
+template <int PREC> __global__ void step_ref_kernel(PhysArgs, LevelArgs, Ctl, int, double);
+template <int PREC> __global__ void moments_kernel(PhysArgs, LevelArgs, Ctl, int, double *, double *, double *);
+template <int PREC> __global__ void get_state_kernel(LevelArgs, Ctl, int, double *);
+template <int PREC> __global__ void set_macro_kernel(PhysArgs, LevelArgs, Ctl, const double *);
+template <int PREC>
+__global__ void stats_accumulate_kernel(PhysArgs, LevelArgs, Ctl, int, int, double *, long long, double *, long long);
+__global__ void stats_finalize_kernel(const double *, long long, long long, double *, double *);
+template <int CPB> __global__ void sort_samples_kernel(double *, long long, int, int);
+__global__ void w1_kernel(const double *, const double *, long long, int, double *, double *);
+__global__ void scale_kernel(double *, double);
+__global__ void fill_kernel(double *, double);
+} // namespace vlbm
+
+using namespace vlbm;
+
+namespace {
+
+thread_local std::string g_err = "no error";
+
+vlbm_status fail(vlbm_status code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+#define HIP_TRY(expr)                                                                   \
+    do {                                                                                \
+        hipError_t e_ = (expr);                                                         \
+        if (e_ != hipSuccess)                                                           \
+            return fail(VLBM_ERR_HIP, "%s failed: %s", #expr, hipGetErrorString(e_));    \
+    } while (0)
+
+#define LAUNCH_CHECK(what)                                                              \
+    do {                                                                                \
+        hipError_t e_ = hipGetLastError();                                              \
+        if (e_ != hipSuccess)                                                           \
+            return fail(VLBM_ERR_HIP, "%s launch failed: %s", what, hipGetErrorString(e_)); \
+    } while (0)
+
+size_t state_bytes(int prec, int nx, int ny, int R)
+{
+    const size_t plane = (size_t)nx * (size_t)ny;
+    if (prec == VLBM_FP64)
+        return (size_t)20 * (size_t)R * plane * sizeof(double);
+    const size_t fbytes = ((size_t)15 * (size_t)R * plane * sizeof(float) + 255) & ~(size_t)255;
+    return fbytes + (size_t)5 * (size_t)R * plane * sizeof(double);
+}
+
+vlbm_status check_params(const vlbm_params *p)
+{
+    if (!p)
+        return fail(VLBM_ERR_ARG, "params is NULL");
+    if (!(p->gamma > 1.0) || !std::isfinite(p->gamma))
+        return fail(VLBM_ERR_ARG, "gamma must be > 1 (got %g)", p->gamma);
+    if (!(p->alpha >= 0.0 && p->alpha < 1.0))
+        return fail(VLBM_ERR_ARG, "alpha must lie in [0, 1) (got %g)", p->alpha);
+    if (!(p->kappa >= 1.0) || !std::isfinite(p->kappa))
+        return fail(VLBM_ERR_ARG, "kappa must be >= 1 (got %g)", p->kappa);
+    if (!(p->rlmp_relax >= 0.0) || !std::isfinite(p->rlmp_relax))
+        return fail(VLBM_ERR_ARG, "rlmp_relax must be >= 0 (got %g)", p->rlmp_relax);
+    if (!(p->pos_eps >= 0.0 && p->pos_eps < 1.0))
+        return fail(VLBM_ERR_ARG, "pos_eps must lie in [0, 1) (got %g)", p->pos_eps);
+    if (!(p->rho_amb > 0.0) || !(p->p_amb > 0.0) || !(p->rho_jet > 0.0) || !(p->r_jet >= 0.0) ||
+        !std::isfinite(p->v_jet) || !std::isfinite(p->kl_amp) || !std::isfinite(p->rho_amb) ||
+        !std::isfinite(p->p_amb) || !std::isfinite(p->rho_jet) || !std::isfinite(p->r_jet))
+        return fail(VLBM_ERR_ARG, "jet constants must be finite with rho_amb, p_amb, rho_jet > 0, r_jet >= 0");
+    if (p->kl_modes < 0 || p->kl_modes > 64)
+        return fail(VLBM_ERR_ARG, "kl_modes must lie in [0, 64] (got %d)", p->kl_modes);
+    if (p->kl_decay < 0 || p->kl_decay > 16)
+        return fail(VLBM_ERR_ARG, "kl_decay must lie in [0, 16] (got %d)", p->kl_decay);
+    if (p->bc < VLBM_BC_JET || p->bc > VLBM_BC_NEUMANN)
+        return fail(VLBM_ERR_ARG, "unknown bc %d", p->bc);
+    if (p->limiter < VLBM_LIMITER_RLMP || p->limiter > VLBM_THETA_ONE)
+        return fail(VLBM_ERR_ARG, "unknown limiter %d", p->limiter);
+    if (p->precision != VLBM_FP64 && p->precision != VLBM_MIXED)
+        return fail(VLBM_ERR_ARG, "unknown precision %d", p->precision);
+    if (p->reserved != 0)
+        return fail(VLBM_ERR_ARG, "reserved must be 0");
+    return VLBM_OK;
+}
+
+vlbm_status check_grid(int nx, int ny, int R)
+{
+    if (nx < 3 || ny < 3)
+        return fail(VLBM_ERR_SIZE, "a level needs nx, ny >= 3 (got %d x %d)", nx, ny);
+    if (R < 1 || R > 65535)
+        return fail(VLBM_ERR_SIZE, "n_real must lie in [1, 65535] (got %d)", R);
+    if ((ny + 3) / 4 > 65535)
+        return fail(VLBM_ERR_SIZE, "ny = %d exceeds the launch grid", ny);
+    if ((double)nx * (double)ny * (double)R * 20.0 > 9.0e15)
+        return fail(VLBM_ERR_SIZE, "level too large");
+    return VLBM_OK;
+}
+
+PhysArgs phys_args(const vlbm_params &p)
+{
+    return PhysArgs{p.gamma, p.alpha, p.kappa, p.rlmp_relax, p.pos_eps, p.rho_amb, p.p_amb, p.rho_jet,
+                    p.v_jet, p.r_jet, p.kl_amp, p.kl_modes, p.kl_decay, p.bc, p.limiter};
+}
+
+dim3 node_grid(const LevelArgs &L) { return dim3((L.nx + 63) / 64, (L.ny + 3) / 4, L.R); }
+
+} // namespace
+
+struct vlbm_ensemble {
+    vlbm_params p;
+    std::vector<LevelArgs> levels;
+    int n_real = 0;
+    hipStream_t stream = nullptr;
+    void *ctl_mem = nullptr;
+    double *coeffs_dev = nullptr;
+    Ctl ctl{};
+    long long n_launch = 0; // launches since the last (re)initialisation: ring phase = n % 3
+};
+
+namespace {
+
+int phase_of(const vlbm_ensemble *e) { return (int)(e->n_launch % 3); }
+
+vlbm_status check_level(const vlbm_ensemble *e, int level)
+{
+    if (!e)
+        return fail(VLBM_ERR_ARG, "ensemble is NULL");
+    if (level < 0 || level >= (int)e->levels.size())
+        return fail(VLBM_ERR_ARG, "level %d out of range [0, %zu)", level, e->levels.size());
+    return VLBM_OK;
+}
+
+// Read the control slot holding the current state into host vectors.
+vlbm_status read_ctl(const vlbm_ensemble *e, std::vector<double> &t, std::vector<long long> &steps,
+                     std::vector<double> &a, std::vector<int> &status)
+{
+    const int nr = e->ctl.nr, ph = phase_of(e);
+    t.resize(nr);
+    steps.resize(nr);
+    a.resize(nr);
+    status.resize(nr);
+    HIP_TRY(hipMemcpyAsync(t.data(), e->ctl.t + (size_t)ph * nr, nr * sizeof(double), hipMemcpyDeviceToHost, e->stream));
+    HIP_TRY(hipMemcpyAsync(steps.data(), e->ctl.steps + (size_t)ph * nr, nr * sizeof(long long), hipMemcpyDeviceToHost, e->stream));
+    HIP_TRY(hipMemcpyAsync(a.data(), e->ctl.a_last + (size_t)ph * nr, nr * sizeof(double), hipMemcpyDeviceToHost, e->stream));
+    HIP_TRY(hipMemcpyAsync(status.data(), e->ctl.status, nr * sizeof(int), hipMemcpyDeviceToHost, e->stream));
+    HIP_TRY(hipStreamSynchronize(e->stream));
+    return VLBM_OK;
+}
+
+} // namespace
+
+extern "C" {
+
+const char *vlbm_last_error(void) { return g_err.c_str(); }
+
+vlbm_status vlbm_state_bytes(const vlbm_params *p, int32_t nx, int32_t ny, int32_t n_real, size_t *bytes)
+{
+    vlbm_status rc = check_params(p);
+    if (rc != VLBM_OK)
+        return rc;
+    if ((rc = check_grid(nx, ny, n_real)) != VLBM_OK)
+        return rc;
+    if (!bytes)
+        return fail(VLBM_ERR_ARG, "bytes is NULL");
+    *bytes = state_bytes(p->precision, nx, ny, n_real);
+    return VLBM_OK;
+}
+
+vlbm_status vlbm_init_ensemble(const vlbm_params *p, const vlbm_level *levels, int32_t n_levels,
+                               const double *coeffs, int32_t n_real, void *hip_stream,
+                               vlbm_ensemble **out)
+{
+    vlbm_status rc = check_params(p);
+    if (rc != VLBM_OK)
+        return rc;
+    if (!out)
+        return fail(VLBM_ERR_ARG, "out is NULL");
+    *out = nullptr;
+    if (!levels || n_levels < 1 || n_levels > 16)
+        return fail(VLBM_ERR_ARG, "need 1..16 levels (got %d)", n_levels);
+    if (p->bc == VLBM_BC_JET && !coeffs && p->kl_modes > 0)
+        return fail(VLBM_ERR_ARG, "coeffs is NULL for the jet problem");
+    for (int l = 0; l < n_levels; ++l) {
+        const vlbm_level &L = levels[l];
+        if ((rc = check_grid(L.nx, L.ny, n_real)) != VLBM_OK)
+            return rc;
+        if (!(L.dx > 0.0) || !std::isfinite(L.dx) || !std::isfinite(L.y_min))
+            return fail(VLBM_ERR_ARG, "level %d: dx must be finite and > 0", l);
+        for (int b = 0; b < 2; ++b)
+            if (!L.state[b] || ((uintptr_t)L.state[b] & 255))
+                return fail(VLBM_ERR_ARG, "level %d: state[%d] must be a non-NULL 256-byte aligned device pointer", l, b);
+    }
+    if (coeffs)
+        for (long long k = 0; k < (long long)n_real * 2 * p->kl_modes; ++k)
+            if (!(coeffs[k] >= -1.0 && coeffs[k] <= 1.0))
+                return fail(VLBM_ERR_ARG, "coeffs[%lld] = %g outside [-1, 1]", k, coeffs[k]);
+    if ((long long)n_real * n_levels > 1 << 24)
+        return fail(VLBM_ERR_SIZE, "too many realizations");
+
+    vlbm_ensemble *e = new vlbm_ensemble();
+    e->p = *p;
+    e->n_real = n_real;
+    e->stream = (hipStream_t)hip_stream;
+    const int nr = n_real * n_levels;
+    for (int l = 0; l < n_levels; ++l) {
+        LevelArgs L{levels[l].nx, levels[l].ny, n_real, l * n_real, levels[l].dx, levels[l].y_min,
+                    {levels[l].state[0], levels[l].state[1]}};
+        e->levels.push_back(L);
+    }
+    const size_t ctl_bytes = (size_t)3 * nr * (sizeof(double) * 2 + sizeof(long long) + sizeof(unsigned long long)) +
+                             (size_t)nr * sizeof(int);
+    hipError_t he = hipMalloc(&e->ctl_mem, ctl_bytes);
+    if (he != hipSuccess) {
+        delete e;
+        return fail(VLBM_ERR_HIP, "hipMalloc(control) failed: %s", hipGetErrorString(he));
+    }
+    char *c = (char *)e->ctl_mem;
+    e->ctl.t = (double *)c;
+    c += 3 * nr * sizeof(double);
+    e->ctl.a_last = (double *)c;
+    c += 3 * nr * sizeof(double);
+    e->ctl.steps = (long long *)c;
+    c += 3 * nr * sizeof(long long);
+    e->ctl.amax = (unsigned long long *)c;
+    c += 3 * nr * sizeof(unsigned long long);
+    e->ctl.status = (int *)c;
+    e->ctl.nr = nr;
+    const size_t ncoef = (size_t)n_real * 2 * p->kl_modes;
+    if (ncoef > 0) {
+        he = hipMalloc(&e->coeffs_dev, ncoef * sizeof(double));
+        if (he == hipSuccess && coeffs)
+            he = hipMemcpyAsync(e->coeffs_dev, coeffs, ncoef * sizeof(double), hipMemcpyHostToDevice, e->stream);
+        if (he == hipSuccess && !coeffs)
+            he = hipMemsetAsync(e->coeffs_dev, 0, ncoef * sizeof(double), e->stream);
+    }
+    if (he == hipSuccess)
+        he = hipMemsetAsync(e->ctl_mem, 0, ctl_bytes, e->stream);
+    if (he != hipSuccess) {
+        vlbm_destroy(e);
+        return fail(VLBM_ERR_HIP, "initialisation copy failed: %s", hipGetErrorString(he));
+    }
+    const PhysArgs ph = phys_args(*p);
+    for (const LevelArgs &L : e->levels) {
+        if (p->precision == VLBM_FP64) {
+            init_macro_kernel<0><<<node_grid(L), 256, 0, e->stream>>>(ph, L, e->coeffs_dev, e->ctl);
+            equilibrium_kernel<0><<<node_grid(L), 256, 0, e->stream>>>(ph, L, e->ctl, 0);
+        } else {
+            init_macro_kernel<1><<<node_grid(L), 256, 0, e->stream>>>(ph, L, e->coeffs_dev, e->ctl);
+            equilibrium_kernel<1><<<node_grid(L), 256, 0, e->stream>>>(ph, L, e->ctl, 0);
+        }
+        hipError_t le = hipGetLastError();
+        if (le != hipSuccess) {
+            vlbm_destroy(e);
+            return fail(VLBM_ERR_HIP, "init launch failed: %s", hipGetErrorString(le));
+        }
+    }
+    // The host coefficient array may be released once this call returns.
+    he = hipStreamSynchronize(e->stream);
+    if (he != hipSuccess) {
+        vlbm_destroy(e);
+        return fail(VLBM_ERR_HIP, "init failed: %s", hipGetErrorString(he));
+    }
+    *out = e;
+    return VLBM_OK;
+}
+
+vlbm_status vlbm_set_macroscopic(vlbm_ensemble *e, int32_t level, const double *u)
+{
+    vlbm_status rc = check_level(e, level);
+    if (rc != VLBM_OK)
+        return rc;
+    if (!u)
+        return fail(VLBM_ERR_ARG, "u is NULL");
+    // Restart the whole ensemble's clock at this level: the other levels keep
+    // their states but the ring is re-based so that slot 0 is current.
+    std::vector<double> t, a;
+    std::vector<long long> steps;
+    std::vector<int> status;
+    if ((rc = read_ctl(e, t, steps, a, status)) != VLBM_OK)
+        return rc;
+    const LevelArgs &L = e->levels[level];
+    for (int m = 0; m < L.R; ++m) {
+        t[L.ctl_off + m] = 0.0;
+        steps[L.ctl_off + m] = 0;
+        a[L.ctl_off + m] = 0.0;
+        status[L.ctl_off + m] = 0;
+    }
+    std::vector<unsigned long long> amax(e->ctl.nr, 0ull);
+    const int nr = e->ctl.nr, ph = phase_of(e);
+    HIP_TRY(hipMemcpyAsync(amax.data(), e->ctl.amax + (size_t)ph * nr, nr * sizeof(unsigned long long), hipMemcpyDeviceToHost, e->stream));
+    HIP_TRY(hipStreamSynchronize(e->stream));
+    for (int m = 0; m < L.R; ++m)
+        amax[L.ctl_off + m] = 0ull;
+    // Other levels: keep their current buffers by keeping their step parity.
+    HIP_TRY(hipMemsetAsync(e->ctl_mem, 0, (size_t)3 * nr * (sizeof(double) * 2 + sizeof(long long) + sizeof(unsigned long long)) + nr * sizeof(int), e->stream));
+    HIP_TRY(hipMemcpyAsync(e->ctl.t, t.data(), nr * sizeof(double), hipMemcpyHostToDevice, e->stream));
+    HIP_TRY(hipMemcpyAsync(e->ctl.steps, steps.data(), nr * sizeof(long long), hipMemcpyHostToDevice, e->stream));
+    HIP_TRY(hipMemcpyAsync(e->ctl.a_last, a.data(), nr * sizeof(double), hipMemcpyHostToDevice, e->stream));
+    HIP_TRY(hipMemcpyAsync(e->ctl.amax, amax.data(), nr * sizeof(unsigned long long), hipMemcpyHostToDevice, e->stream));
+    HIP_TRY(hipMemcpyAsync(e->ctl.status, status.data(), nr * sizeof(int), hipMemcpyHostToDevice, e->stream));
+    e->n_launch = 0;
+    const PhysArgs ph_args = phys_args(e->p);
+    if (e->p.precision == VLBM_FP64) {
+        set_macro_kernel<0><<<node_grid(L), 256, 0, e->stream>>>(ph_args, L, e->ctl, u);
+        equilibrium_kernel<0><<<node_grid(L), 256, 0, e->stream>>>(ph_args, L, e->ctl, 0);
+    } else {
+        set_macro_kernel<1><<<node_grid(L), 256, 0, e->stream>>>(ph_args, L, e->ctl, u);
+        equilibrium_kernel<1><<<node_grid(L), 256, 0, e->stream>>>(ph_args, L, e->ctl, 0);
+    }
+    LAUNCH_CHECK("set_macroscopic");
+    HIP_TRY(hipStreamSynchronize(e->stream));
+    return VLBM_OK;
+}
+
+vlbm_status vlbm_step(vlbm_ensemble *e, double t_final, int32_t n_steps, int32_t *all_done)
+{
+    if (!e)
+        return fail(VLBM_ERR_ARG, "ensemble is NULL");
+    if (!std::isfinite(t_final))
+        return fail(VLBM_ERR_ARG, "t_final must be finite");
+    if (n_steps < 0)
+        return fail(VLBM_ERR_ARG, "n_steps must be >= 0");
+    const PhysArgs ph = phys_args(e->p);
+    for (int s = 0; s < n_steps; ++s) {
+        const int phase = phase_of(e);
+        for (const LevelArgs &L : e->levels) {
+            if (e->p.precision == VLBM_FP64)
+                step_ref_kernel<0><<<node_grid(L), 256, 0, e->stream>>>(ph, L, e->ctl, phase, t_final);
+            else
+                step_ref_kernel<1><<<node_grid(L), 256, 0, e->stream>>>(ph, L, e->ctl, phase, t_final);
+        }
+        LAUNCH_CHECK("step");
+        e->n_launch++;
+    }
+    if (all_done) {
+        std::vector<double> t, a;
+        std::vector<long long> steps;
+        std::vector<int> status;
+        vlbm_status rc = read_ctl(e, t, steps, a, status);
+        if (rc != VLBM_OK)
+            return rc;
+        int done = 1;
+        for (int k = 0; k < e->ctl.nr; ++k) {
+            if (status[k] & STATUS_NONFINITE)
+                return fail(VLBM_ERR_NONFINITE, "realization %d of level %d produced a non-finite value",
+                            k % e->n_real, k / e->n_real);
+            if (status[k] & STATUS_NONPOSITIVE)
+                return fail(VLBM_ERR_NONPOSITIVE, "realization %d of level %d produced rho <= 0 or p <= 0",
+                            k % e->n_real, k / e->n_real);
+            if (!(t[k] >= t_final))
+                done = 0;
+        }
+        *all_done = done;
+    }
+    return VLBM_OK;
+}
+
+vlbm_status vlbm_times(const vlbm_ensemble *e, int32_t level, double *t_out, int64_t *steps_out,
+                       double *a_out, int32_t *status_out)
+{
+    vlbm_status rc = check_level(e, level);
+    if (rc != VLBM_OK)
+        return rc;
+    std::vector<double> t, a;
+    std::vector<long long> steps;
+    std::vector<int> status;
+    if ((rc = read_ctl(e, t, steps, a, status)) != VLBM_OK)
+        return rc;
+    const LevelArgs &L = e->levels[level];
+    for (int m = 0; m < L.R; ++m) {
+        const int k = L.ctl_off + m;
+        if (t_out)
+            t_out[m] = t[k];
+        if (steps_out)
+            steps_out[m] = steps[k];
+        if (a_out)
+            a_out[m] = a[k];
+        if (status_out)
+            status_out[m] = (status[k] & STATUS_NONFINITE) ? VLBM_ERR_NONFINITE
+                            : (status[k] & STATUS_NONPOSITIVE) ? VLBM_ERR_NONPOSITIVE : VLBM_OK;
+    }
+    return VLBM_OK;
+}
+
+vlbm_status vlbm_get_state(const vlbm_ensemble *e, int32_t level, double *out)
+{
+    vlbm_status rc = check_level(e, level);
+    if (rc != VLBM_OK)
+        return rc;
+    if (!out)
+        return fail(VLBM_ERR_ARG, "out is NULL");
+    const LevelArgs &L = e->levels[level];
+    if (e->p.precision == VLBM_FP64)
+        get_state_kernel<0><<<node_grid(L), 256, 0, e->stream>>>(L, e->ctl, phase_of(e), out);
+    else
+        get_state_kernel<1><<<node_grid(L), 256, 0, e->stream>>>(L, e->ctl, phase_of(e), out);
+    LAUNCH_CHECK("get_state");
+    return VLBM_OK;
+}
+
+vlbm_status vlbm_moments(const vlbm_ensemble *e, int32_t level, double *rho, double *speed, double *p)
+{
+    vlbm_status rc = check_level(e, level);
+    if (rc != VLBM_OK)
+        return rc;
+    if (!rho && !speed && !p)
+        return VLBM_OK;
+    const LevelArgs &L = e->levels[level];
+    const PhysArgs ph = phys_args(e->p);
+    if (e->p.precision == VLBM_FP64)
+        moments_kernel<0><<<node_grid(L), 256, 0, e->stream>>>(ph, L, e->ctl, phase_of(e), rho, speed, p);
+    else
+        moments_kernel<1><<<node_grid(L), 256, 0, e->stream>>>(ph, L, e->ctl, phase_of(e), rho, speed, p);
+    LAUNCH_CHECK("moments");
+    return VLBM_OK;
+}
+
+vlbm_status vlbm_ensemble_stats(const vlbm_ensemble *e, int32_t level, int32_t r, double *acc,
+                                int64_t n_prev, double *samples, int64_t m_offset)
+{
+    vlbm_status rc = check_level(e, level);
+    if (rc != VLBM_OK)
+        return rc;
+    const LevelArgs &L = e->levels[level];
+    if (r < 1 || L.nx % r || L.ny % r)
+        return fail(VLBM_ERR_ARG, "restriction factor %d must divide %d x %d", r, L.nx, L.ny);
+    if (!acc)
+        return fail(VLBM_ERR_ARG, "acc is NULL");
+    if (n_prev < 0 || m_offset < 0)
+        return fail(VLBM_ERR_ARG, "n_prev and m_offset must be >= 0");
+    const long long ncell = (long long)(L.nx / r) * (L.ny / r);
+    const PhysArgs ph = phys_args(e->p);
+    const dim3 grid((unsigned)((ncell + 255) / 256));
+    if (e->p.precision == VLBM_FP64)
+        stats_accumulate_kernel<0><<<grid, 256, 0, e->stream>>>(ph, L, e->ctl, phase_of(e), r, acc, n_prev, samples, m_offset);
+    else
+        stats_accumulate_kernel<1><<<grid, 256, 0, e->stream>>>(ph, L, e->ctl, phase_of(e), r, acc, n_prev, samples, m_offset);
+    LAUNCH_CHECK("ensemble_stats");
+    return VLBM_OK;
+}
+
+vlbm_status vlbm_stats_finalize(const double *acc, int64_t n_cells, int64_t n_total, double *mean,
+                                double *std_out, void *hip_stream)
+{
+    if (!acc)
+        return fail(VLBM_ERR_ARG, "acc is NULL");
+    if (n_cells < 1 || n_total < 1)
+        return fail(VLBM_ERR_ARG, "n_cells and n_total must be >= 1");
+    if (!mean && !std_out)
+        return VLBM_OK;
+    stats_finalize_kernel<<<(unsigned)((n_cells + 255) / 256), 256, 0, (hipStream_t)hip_stream>>>(
+        acc, n_cells, n_total, mean, std_out);
+    LAUNCH_CHECK("stats_finalize");
+    return VLBM_OK;
+}
+
+vlbm_status vlbm_sort_samples(double *samples, int64_t n_cells, int32_t m, void *hip_stream)
+{
+    if (!samples)
+        return fail(VLBM_ERR_ARG, "samples is NULL");
+    if (n_cells < 1 || m < 1 || m > 4096)
+        return fail(VLBM_ERR_SIZE, "need n_cells >= 1 and 1 <= m <= 4096 (got %lld, %d)", (long long)n_cells, m);
+    int mp = 1;
+    while (mp < m)
+        mp <<= 1;
+    if (mp < 2)
+        mp = 2;
+    hipStream_t st = (hipStream_t)hip_stream;
+    if (mp <= 256) {
+        sort_samples_kernel<16><<<(unsigned)((n_cells + 15) / 16), 256, 16 * mp * sizeof(double), st>>>(samples, n_cells, m, mp);
+    } else if (mp <= 1024) {
+        sort_samples_kernel<4><<<(unsigned)((n_cells + 3) / 4), 256, 4 * mp * sizeof(double), st>>>(samples, n_cells, m, mp);
+    } else {
+        sort_samples_kernel<1><<<(unsigned)n_cells, 256, mp * sizeof(double), st>>>(samples, n_cells, m, mp);
+    }
+    LAUNCH_CHECK("sort_samples");
+    return VLBM_OK;
+}
+
+vlbm_status vlbm_w1(const double *a, const double *b, int64_t n_cells, int32_t m, double *w1_cell,
+                    double *w1_mean, void *hip_stream)
+{
+    if (!a || !b)
+        return fail(VLBM_ERR_ARG, "sample stores must be non-NULL");
+    if (n_cells < 1 || m < 1)
+        return fail(VLBM_ERR_SIZE, "need n_cells >= 1 and m >= 1");
+    hipStream_t st = (hipStream_t)hip_stream;
+    if (w1_mean)
+        fill_kernel<<<1, 64, 0, st>>>(w1_mean, 0.0);
+    w1_kernel<<<(unsigned)((n_cells + 255) / 256), 256, 0, st>>>(a, b, n_cells, m, w1_cell, w1_mean);
+    if (w1_mean)
+        scale_kernel<<<1, 64, 0, st>>>(w1_mean, 1.0 / (double)n_cells);
+    LAUNCH_CHECK("w1");
+    return VLBM_OK;
+}
+
+vlbm_status vlbm_destroy(vlbm_ensemble *e)
+{
+    if (!e)
+        return VLBM_OK;
+    (void)hipStreamSynchronize(e->stream);
+    if (e->ctl_mem)
+        (void)hipFree(e->ctl_mem);
+    if (e->coeffs_dev)
+        (void)hipFree(e->coeffs_dev);
+    delete e;
+    return VLBM_OK;
+}
+
+} // extern "C"

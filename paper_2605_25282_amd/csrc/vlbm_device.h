@@ -1,0 +1,342 @@
+// vlbm_device.h -- device-side building blocks of the VLBM ensemble library
+// (gfx950).  Internal header of the HIP library; not part of the public ABI.
+//
+// Floating-point contract: this library is compiled with -ffp-contract=off and
+// without fast-math, and every expression below is written so that its
+// operation order is fixed.  The blended update with the limiter amplifies a
+// one-ulp difference by roughly 1.5 per step at Mach 2000 (Sec. 2.2 setup), so
+// the FP64 path is written to be bitwise reproducible: correctly rounded
+// division and square root, correctly rounded cos/sin for the inlet profile,
+// no reassociation.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace vlbm {
+
+// ---------------------------------------------------------------------------
+// Scheme parameters resolved for one time step.
+// ---------------------------------------------------------------------------
+struct Phys {
+    double gamma;      // heat-capacity ratio (eq:eos)
+    double alpha;      // rest-population weight (eq:maxwellians5)
+    double w;          // (1 - alpha) / 4, weight of M_1..M_4
+    double h;          // 1 / (2 a), a = kinetic speed of the step
+    double rlmp_relax; // relaxation of the local density bounds
+    double pos_eps;    // internal-energy floor (fraction of the low-order value)
+};
+
+// ---------------------------------------------------------------------------
+// Pointwise physics (eq:eos, eq:fluxF, eq:fluxG, eq:maxwellians12-34)
+// ---------------------------------------------------------------------------
+
+// D2Q5 Maxwellians M_1..M_4 of the state u: M[k][v], k = 0..3.
+__device__ __forceinline__ void maxwellians(const Phys &P, const double u[4], double M[4][4])
+{
+    const double rho = u[0], m1 = u[1], m2 = u[2], E = u[3];
+    const double v1 = m1 / rho;
+    const double v2 = m2 / rho;
+    const double p = (P.gamma - 1.0) * (E - 0.5 * rho * (v1 * v1 + v2 * v2));
+    const double f[4] = {m1, m1 * v1 + p, m1 * v2, (E + p) * v1};
+    const double g[4] = {m2, m2 * v1, m2 * v2 + p, (E + p) * v2};
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        const double wu = P.w * u[v];
+        M[0][v] = wu + P.h * f[v];
+        M[1][v] = wu - P.h * f[v];
+        M[2][v] = wu + P.h * g[v];
+        M[3][v] = wu - P.h * g[v];
+    }
+}
+
+// Largest characteristic speed max(|v1|,|v2|) + c of the state u; *bad is set
+// when rho <= 0, p <= 0 or a value is not finite.
+__device__ __forceinline__ double wave_speed(double gamma, const double u[4], int *bad)
+{
+    const double rho = u[0];
+    const double v1 = u[1] / rho;
+    const double v2 = u[2] / rho;
+    const double p = (gamma - 1.0) * (u[3] - 0.5 * rho * (v1 * v1 + v2 * v2));
+    if (!(rho > 0.0) || !(p > 0.0) || !isfinite(rho) || !isfinite(p)) {
+        *bad = 1;
+        return 0.0;
+    }
+    const double c = sqrt(gamma * p / rho);
+    return fmax(fabs(v1), fabs(v2)) + c;
+}
+
+// Relaxed local density bounds and low-order internal energy of a cell whose
+// low-order state is L, from the densities of its four bar states M_k/w
+// (M1w = M_1 of the west neighbour, ...) and, if alpha > 0, its own density.
+__device__ __forceinline__ void cell_bounds(const Phys &P, const double L[4], double m1w_rho,
+                                            double m2e_rho, double m3s_rho, double m4n_rho,
+                                            double rho_c, double *rmin_out, double *rmax_out,
+                                            double *rhoe_out)
+{
+    const double b1 = m1w_rho / P.w, b2 = m2e_rho / P.w, b3 = m3s_rho / P.w, b4 = m4n_rho / P.w;
+    double rmax = fmax(fmax(b1, b2), fmax(b3, b4));
+    double rmin = fmin(fmin(b1, b2), fmin(b3, b4));
+    if (P.alpha > 0.0) {
+        rmax = fmax(rmax, rho_c);
+        rmin = fmin(rmin, rho_c);
+    }
+    const double delta = P.rlmp_relax * (rmax - rmin);
+    *rmax_out = rmax + delta;
+    *rmin_out = fmax(rmin - delta, 0.5 * rmin);
+    *rhoe_out = L[3] - 0.5 * (L[1] * L[1] + L[2] * L[2]) / L[0];
+}
+
+// Largest theta in [0,1] keeping L + theta*D inside [rmin, rmax] in density and
+// above pos_eps * rhoeL in internal energy (the quadratic
+// Q = rho E - |m|^2/2 - eps rhoeL rho has the sign of the constraint for rho > 0).
+__device__ __forceinline__ double side_theta(const Phys &P, const double L[4], double rmin,
+                                             double rmax, double rhoeL, const double D[4])
+{
+    double th = 1.0;
+    if (D[0] > 0.0)
+        th = (rmax - L[0]) / D[0];
+    else if (D[0] < 0.0)
+        th = (rmin - L[0]) / D[0];
+    th = fmin(fmax(th, 0.0), 1.0);
+
+    if (!(rhoeL > 0.0))
+        return 0.0;
+    const double eps = P.pos_eps;
+    const double c2 = D[0] * D[3] - 0.5 * (D[1] * D[1] + D[2] * D[2]);
+    const double c1 = L[0] * D[3] + D[0] * L[3] - (L[1] * D[1] + L[2] * D[2]) - eps * rhoeL * D[0];
+    const double c0 = (1.0 - eps) * L[0] * rhoeL;
+    const double q = c0 + th * (c1 + th * c2);
+    if (q >= 0.0)
+        return th;
+    double disc = c1 * c1 - 4.0 * c2 * c0;
+    if (disc < 0.0)
+        disc = 0.0;
+    const double sq = sqrt(disc);
+    double r;
+    if (c1 < 0.0)
+        r = 2.0 * c0 / (sq - c1);
+    else if (c2 < 0.0)
+        r = (c1 + sq) / (-2.0 * c2);
+    else
+        r = 0.0;
+    return fmin(fmax(r, 0.0), th);
+}
+
+// ---------------------------------------------------------------------------
+// Correctly rounded cos / sin (inlet profile, eq:karhunenExp).
+// Double-double arithmetic (Dekker 1971; Knuth's TwoSum), Cody-Waite reduction
+// by pi/2 split into three doubles, Taylor series of degree 27 on |r| <= pi/4.
+// The double-double result carries ~100 correct bits, so rounding it once to
+// double gives the correctly rounded value except in cases closer than
+// ~2^-100 to a rounding boundary.
+// ---------------------------------------------------------------------------
+struct dd {
+    double hi, lo;
+};
+__device__ __forceinline__ dd dd_two_sum(double a, double b)
+{
+    const double s = a + b;
+    const double bb = s - a;
+    return {s, (a - (s - bb)) + (b - bb)};
+}
+__device__ __forceinline__ dd dd_fast_two_sum(double a, double b)
+{
+    const double s = a + b;
+    return {s, b - (s - a)};
+}
+__device__ __forceinline__ dd dd_two_prod(double a, double b)
+{
+    const double p = a * b;
+    return {p, __builtin_fma(a, b, -p)};
+}
+__device__ __forceinline__ dd dd_add(dd a, dd b)
+{
+    dd s = dd_two_sum(a.hi, b.hi);
+    const dd t = dd_two_sum(a.lo, b.lo);
+    s.lo += t.hi;
+    s = dd_fast_two_sum(s.hi, s.lo);
+    s.lo += t.lo;
+    return dd_fast_two_sum(s.hi, s.lo);
+}
+__device__ __forceinline__ dd dd_mul(dd a, dd b)
+{
+    dd p = dd_two_prod(a.hi, b.hi);
+    p.lo += a.hi * b.lo + a.lo * b.hi;
+    return dd_fast_two_sum(p.hi, p.lo);
+}
+__device__ __forceinline__ dd dd_div_d(dd a, double b)
+{
+    const double q1 = a.hi / b;
+    const dd p = dd_two_prod(q1, b);
+    dd r = dd_two_sum(a.hi, -p.hi);
+    r.lo -= p.lo;
+    r.lo += a.lo;
+    const double q2 = (r.hi + r.lo) / b;
+    return dd_fast_two_sum(q1, q2);
+}
+
+// sin and cos of x (|x| < 2^20), correctly rounded to double.
+__device__ inline void cr_sincos(double x, double *s_out, double *c_out)
+{
+    const double pio2_1 = 0x1.921fb54442d18p+0;    // pi/2 = pio2_1 + pio2_2 + pio2_3 + O(2^-164)
+    const double pio2_2 = 0x1.1a62633145c07p-54;
+    const double pio2_3 = -0x1.f1976b7ed8fbcp-110;
+    const double n = rint(x * 0x1.45f306dc9c883p-1); // x * 2/pi
+    const dd p1 = dd_two_prod(n, pio2_1);
+    dd r = dd_two_sum(x, -p1.hi);
+    r.lo -= p1.lo;
+    r = dd_fast_two_sum(r.hi, r.lo);
+    const dd p2 = dd_two_prod(n, pio2_2);
+    r = dd_add(r, dd{-p2.hi, -p2.lo});
+    r = dd_add(r, dd{-n * pio2_3, 0.0});
+    // Taylor coefficients 1/k!, k = 0..27, in double-double.
+    dd cs[14], cc[14];
+    dd f = {1.0, 0.0};
+    cc[0] = f;
+    for (int k = 1; k < 28; ++k) {
+        f = dd_div_d(f, (double)k);
+        if (k & 1)
+            cs[k >> 1] = ((k >> 1) & 1) ? dd{-f.hi, -f.lo} : f;
+        else
+            cc[k >> 1] = ((k >> 1) & 1) ? dd{-f.hi, -f.lo} : f;
+    }
+    const dd r2 = dd_mul(r, r);
+    dd ts = cs[13], tc = cc[13];
+    for (int k = 12; k >= 0; --k) {
+        ts = dd_add(dd_mul(ts, r2), cs[k]);
+        tc = dd_add(dd_mul(tc, r2), cc[k]);
+    }
+    const dd sr = dd_mul(ts, r), cr = tc;
+    const int q = ((int)n) & 3;
+    dd s, c;
+    if (q == 0) { s = sr; c = cr; }
+    else if (q == 1) { s = cr; c = dd{-sr.hi, -sr.lo}; }
+    else if (q == 2) { s = dd{-sr.hi, -sr.lo}; c = dd{-cr.hi, -cr.lo}; }
+    else { s = dd{-cr.hi, -cr.lo}; c = sr; }
+    *s_out = s.hi + s.lo;
+    *c_out = c.hi + c.lo;
+}
+
+// ---------------------------------------------------------------------------
+// Per-realization control block, ring-buffered over three launches: launch n
+// reads slot n%3, writes slot (n+1)%3 and clears the maximum of slot (n+2)%3.
+// ---------------------------------------------------------------------------
+struct Ctl {
+    double *t;              // [3][NR] time
+    long long *steps;       // [3][NR] step count
+    double *a_last;         // [3][NR] kinetic speed of the last step
+    unsigned long long *amax; // [3][NR] max wave speed of the state (bits of a double >= 0)
+    int *status;            // [NR] latched failure bits (1 nonpositive, 2 nonfinite)
+    int nr;                 // NR = number of (level, realization) pairs
+};
+
+enum { STATUS_NONPOSITIVE = 1, STATUS_NONFINITE = 2 };
+
+// Bit pattern of a non-negative double, monotone in its value.
+__device__ __forceinline__ unsigned long long ordered_bits(double x)
+{
+    return (unsigned long long)__double_as_longlong(x);
+}
+
+// Block-wide max of v (every thread passes its value), then one atomicMax.
+template <int NT>
+__device__ __forceinline__ void block_atomic_max(double v, unsigned long long *dst)
+{
+    __shared__ double red[NT / 64];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1)
+        v = fmax(v, __shfl_xor(v, o, 64));
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 0)
+        red[wid] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double m = red[0];
+#pragma unroll
+        for (int k = 1; k < NT / 64; ++k)
+            m = fmax(m, red[k]);
+        atomicMax(dst, ordered_bits(m));
+    }
+}
+
+// Time-step control shared by every block of one realization: kinetic speed
+// a = kappa*2*max/(1-alpha), dt = dx/a, shortened near t_final exactly as the
+// oracle does (reading R9).
+struct StepCtl {
+    double a, t_new;
+    bool active;
+};
+__device__ __forceinline__ StepCtl step_control(double t, double amax, double kappa, double alpha,
+                                                double dx, double t_final)
+{
+    StepCtl c;
+    c.active = t < t_final;
+    double a = kappa * 2.0 * amax / (1.0 - alpha);
+    double dt = dx / a;
+    if (t + dt >= t_final) {
+        dt = t_final - t;
+        a = dx / dt;
+        c.t_new = t_final;
+    } else if (t + 2.0 * dt > t_final) {
+        dt = 0.5 * (t_final - t);
+        a = dx / dt;
+        c.t_new = t + dt;
+    } else {
+        c.t_new = t + dt;
+    }
+    c.a = a;
+    return c;
+}
+
+// ---------------------------------------------------------------------------
+// State access.  FP64: double [4 var][5 slot][R][ny][nx].  Mixed: the var 0..2
+// planes as float (same index), padded to 256 B, then the var 3 planes as double.
+// ---------------------------------------------------------------------------
+struct StateFP64 {
+    double *p;
+    size_t plane; // ny * nx
+    int R;
+    __device__ __forceinline__ size_t idx(int v, int s, int m, size_t node) const
+    {
+        return ((size_t)(v * 5 + s) * (size_t)R + (size_t)m) * plane + node;
+    }
+    __device__ __forceinline__ double ld(int v, int s, int m, size_t node) const { return p[idx(v, s, m, node)]; }
+    __device__ __forceinline__ void st(int v, int s, int m, size_t node, double x) const { p[idx(v, s, m, node)] = x; }
+};
+
+struct StateMixed {
+    float *pf;   // var 0..2
+    double *pd;  // var 3
+    size_t plane;
+    int R;
+    __device__ __forceinline__ double ld(int v, int s, int m, size_t node) const
+    {
+        if (v < 3)
+            return (double)pf[((size_t)(v * 5 + s) * (size_t)R + (size_t)m) * plane + node];
+        return pd[((size_t)s * (size_t)R + (size_t)m) * plane + node];
+    }
+    __device__ __forceinline__ void st(int v, int s, int m, size_t node, double x) const
+    {
+        if (v < 3)
+            pf[((size_t)(v * 5 + s) * (size_t)R + (size_t)m) * plane + node] = (float)x;
+        else
+            pd[((size_t)s * (size_t)R + (size_t)m) * plane + node] = x;
+    }
+};
+
+// Launch arguments of one mesh level and of the physics (plain values).
+struct LevelArgs {
+    int nx, ny, R;   // nodes incl. layers, realizations
+    int ctl_off;     // index of realization 0 of this level in the control arrays
+    double dx, y_min;
+    void *buf[2];    // ping-pong state buffers
+};
+
+struct PhysArgs {
+    double gamma, alpha, kappa, rlmp_relax, pos_eps;
+    double rho_amb, p_amb, rho_jet, v_jet, r_jet, kl_amp;
+    int kl_modes, kl_decay, bc, limiter;
+};
+
+} // namespace vlbm

@@ -1,0 +1,266 @@
+"""Python binding of the C ABI in include/vlbm.h (libvlbm_hip.so, gfx950).
+
+Argument marshalling only: every step of the method runs in the HIP kernels of
+the library.  PyTorch provides device memory (``torch.empty(..., device="cuda")``)
+and the HIP stream (``torch.cuda.current_stream().cuda_stream``).  Importing this
+module does not need a GPU; loading the library fails loudly if it was not
+built (see ``paper_2605_25282_amd.build``).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libvlbm_hip.so")
+HEADER_PATH = os.path.join(os.path.dirname(_HERE), "include", "vlbm.h")
+
+OK, ERR_ARG, ERR_HIP, ERR_SIZE, ERR_NONPOSITIVE, ERR_NONFINITE, ERR_STATE = 0, -1, -2, -3, -4, -5, -6
+BC = {"jet": 0, "periodic": 1, "neumann": 2}
+LIMITER = {"limiter": 0, "zero": 1, "one": 2}
+PRECISION = {"fp64": 0, "mixed": 1}
+
+
+class VlbmError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"vlbm error {code}: {msg}")
+        self.code = code
+
+
+class Params(ctypes.Structure):
+    """vlbm_params of include/vlbm.h, with the Mach-2000 jet defaults (Sec. 2.2)."""
+    _fields_ = [("gamma", ctypes.c_double), ("alpha", ctypes.c_double),
+                ("kappa", ctypes.c_double), ("rlmp_relax", ctypes.c_double),
+                ("pos_eps", ctypes.c_double), ("rho_amb", ctypes.c_double),
+                ("p_amb", ctypes.c_double), ("rho_jet", ctypes.c_double),
+                ("v_jet", ctypes.c_double), ("r_jet", ctypes.c_double),
+                ("kl_amp", ctypes.c_double), ("kl_modes", ctypes.c_int32),
+                ("kl_decay", ctypes.c_int32), ("bc", ctypes.c_int32),
+                ("limiter", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+    @classmethod
+    def jet(cls, **kw) -> "Params":
+        d = dict(gamma=5.0 / 3.0, alpha=0.0, kappa=1.0, rlmp_relax=0.1, pos_eps=1e-2,
+                 rho_amb=0.5, p_amb=0.4127, rho_jet=5.0, v_jet=800.0, r_jet=0.05, kl_amp=0.1,
+                 kl_modes=10, kl_decay=2, bc="jet", limiter="limiter", precision="fp64")
+        d.update(kw)
+        d["bc"] = BC[d["bc"]] if isinstance(d["bc"], str) else d["bc"]
+        d["limiter"] = LIMITER[d["limiter"]] if isinstance(d["limiter"], str) else d["limiter"]
+        d["precision"] = (PRECISION[d["precision"]] if isinstance(d["precision"], str)
+                          else d["precision"])
+        return cls(**d, reserved=0)
+
+
+class Level(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("dx", ctypes.c_double),
+                ("y_min", ctypes.c_double), ("state", ctypes.c_void_p * 2)]
+
+
+_lib = None
+_VP = ctypes.c_void_p
+_DP = ctypes.POINTER(ctypes.c_double)
+
+
+def header_functions() -> list[str]:
+    """Names of the functions declared in include/vlbm.h."""
+    txt = open(HEADER_PATH).read()
+    return sorted(set(re.findall(r"^\s*(?:vlbm_status|const char \*)\s*(vlbm_\w+)\(", txt, re.M)))
+
+
+def lib():
+    """Load libvlbm_hip.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with "
+                              "`python -m paper_2605_25282_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        P = ctypes.POINTER(Params)
+        i32, i64, dbl = ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+        sig = {
+            "vlbm_last_error": ([], ctypes.c_char_p),
+            "vlbm_state_bytes": ([P, i32, i32, i32, ctypes.POINTER(ctypes.c_size_t)], i32),
+            "vlbm_init_ensemble": ([P, ctypes.POINTER(Level), i32, _DP, i32, _VP,
+                                    ctypes.POINTER(_VP)], i32),
+            "vlbm_set_macroscopic": ([_VP, i32, _VP], i32),
+            "vlbm_step": ([_VP, dbl, i32, ctypes.POINTER(i32)], i32),
+            "vlbm_times": ([_VP, i32, _DP, ctypes.POINTER(i64), _DP, ctypes.POINTER(i32)], i32),
+            "vlbm_get_state": ([_VP, i32, _VP], i32),
+            "vlbm_moments": ([_VP, i32, _VP, _VP, _VP], i32),
+            "vlbm_ensemble_stats": ([_VP, i32, i32, _VP, i64, _VP, i64], i32),
+            "vlbm_stats_finalize": ([_VP, i64, i64, _VP, _VP, _VP], i32),
+            "vlbm_sort_samples": ([_VP, i64, i32, _VP], i32),
+            "vlbm_w1": ([_VP, _VP, i64, i32, _VP, _VP, _VP], i32),
+            "vlbm_destroy": ([_VP], i32),
+        }
+        for name, (args, res) in sig.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = res
+        _lib = L
+    return _lib
+
+
+def last_error() -> str:
+    return lib().vlbm_last_error().decode()
+
+
+def _check(rc: int) -> None:
+    if rc != OK:
+        raise VlbmError(rc, last_error())
+
+
+def _ptr(t) -> _VP:
+    """Device pointer of a torch tensor (or None)."""
+    return None if t is None else _VP(t.data_ptr())
+
+
+def _stream(stream=None) -> _VP:
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return _VP(s.cuda_stream)
+
+
+def vlbm_state_bytes(p: Params, nx: int, ny: int, n_real: int) -> int:
+    out = ctypes.c_size_t(0)
+    _check(lib().vlbm_state_bytes(ctypes.byref(p), nx, ny, n_real, ctypes.byref(out)))
+    return out.value
+
+
+def vlbm_init_ensemble(p: Params, levels: list[Level], coeffs: np.ndarray | None, n_real: int,
+                       stream=None) -> _VP:
+    arr = (Level * len(levels))(*levels)
+    c = None
+    if coeffs is not None:
+        coeffs = np.ascontiguousarray(coeffs, dtype=np.float64)
+        c = coeffs.ctypes.data_as(_DP)
+    h = _VP()
+    _check(lib().vlbm_init_ensemble(ctypes.byref(p), arr, len(levels), c, n_real,
+                                    _stream(stream), ctypes.byref(h)))
+    return h
+
+
+def vlbm_set_macroscopic(h, level: int, u) -> None:
+    _check(lib().vlbm_set_macroscopic(h, level, _ptr(u)))
+
+
+def vlbm_step(h, t_final: float, n_steps: int, want_done: bool = True):
+    done = ctypes.c_int32(0)
+    _check(lib().vlbm_step(h, t_final, n_steps, ctypes.byref(done) if want_done else None))
+    return bool(done.value) if want_done else None
+
+
+def vlbm_times(h, level: int, n_real: int):
+    t = np.zeros(n_real)
+    s = np.zeros(n_real, dtype=np.int64)
+    a = np.zeros(n_real)
+    st = np.zeros(n_real, dtype=np.int32)
+    _check(lib().vlbm_times(h, level, t.ctypes.data_as(_DP),
+                            s.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                            a.ctypes.data_as(_DP),
+                            st.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))))
+    return t, s, a, st
+
+
+def vlbm_get_state(h, level: int, out) -> None:
+    _check(lib().vlbm_get_state(h, level, _ptr(out)))
+
+
+def vlbm_moments(h, level: int, rho=None, speed=None, p=None) -> None:
+    _check(lib().vlbm_moments(h, level, _ptr(rho), _ptr(speed), _ptr(p)))
+
+
+def vlbm_ensemble_stats(h, level: int, r: int, acc, n_prev: int, samples=None,
+                        m_offset: int = 0) -> None:
+    _check(lib().vlbm_ensemble_stats(h, level, r, _ptr(acc), n_prev, _ptr(samples), m_offset))
+
+
+def vlbm_stats_finalize(acc, n_cells: int, n_total: int, mean=None, std=None, stream=None) -> None:
+    _check(lib().vlbm_stats_finalize(_ptr(acc), n_cells, n_total, _ptr(mean), _ptr(std),
+                                     _stream(stream)))
+
+
+def vlbm_sort_samples(samples, n_cells: int, m: int, stream=None) -> None:
+    _check(lib().vlbm_sort_samples(_ptr(samples), n_cells, m, _stream(stream)))
+
+
+def vlbm_w1(a, b, n_cells: int, m: int, w1_cell=None, w1_mean=None, stream=None) -> None:
+    _check(lib().vlbm_w1(_ptr(a), _ptr(b), n_cells, m, _ptr(w1_cell), _ptr(w1_mean),
+                         _stream(stream)))
+
+
+def vlbm_destroy(h) -> None:
+    _check(lib().vlbm_destroy(h))
+
+
+class Ensemble:
+    """Convenience owner of the device buffers of one ensemble (torch tensors).
+
+    levels: list of (nx, ny, dx, y_min).  The state buffers are allocated here
+    with torch and handed to the library; everything else is a direct call of
+    the C ABI."""
+
+    def __init__(self, params: Params, levels, coeffs, n_real: int, stream=None):
+        import torch
+        self.params, self.n_real = params, n_real
+        self.shapes = [(int(nx), int(ny)) for (nx, ny, _, _) in levels]
+        self.buffers = []
+        lv = []
+        for (nx, ny, dx, y_min) in levels:
+            nbytes = vlbm_state_bytes(params, int(nx), int(ny), n_real)
+            bufs = [torch.empty(nbytes, dtype=torch.uint8, device="cuda") for _ in range(2)]
+            self.buffers.append(bufs)
+            lv.append(Level(int(nx), int(ny), float(dx), float(y_min),
+                            (_VP * 2)(bufs[0].data_ptr(), bufs[1].data_ptr())))
+        self.h = vlbm_init_ensemble(params, lv, coeffs, n_real, stream)
+
+    def close(self) -> None:
+        if self.h is not None:
+            vlbm_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def step(self, t_final: float, n_steps: int, want_done: bool = True):
+        return vlbm_step(self.h, t_final, n_steps, want_done)
+
+    def run(self, t_final: float, chunk: int = 64, max_steps: int = 1 << 30) -> int:
+        """Step until every realization has reached t_final; returns launches made."""
+        n = 0
+        while n < max_steps:
+            k = min(chunk, max_steps - n)
+            done = self.step(t_final, k)
+            n += k
+            if done:
+                break
+        return n
+
+    def times(self, level: int = 0):
+        return vlbm_times(self.h, level, self.n_real)
+
+    def state(self, level: int = 0):
+        """Current state as a float64 tensor [4 var][5 slot][R][ny][nx]."""
+        import torch
+        nx, ny = self.shapes[level]
+        out = torch.empty((4, 5, self.n_real, ny, nx), dtype=torch.float64, device="cuda")
+        vlbm_get_state(self.h, level, out)
+        return out
+
+    def set_macroscopic(self, level: int, u) -> None:
+        vlbm_set_macroscopic(self.h, level, u)
+
+    def moments(self, level: int = 0):
+        import torch
+        nx, ny = self.shapes[level]
+        out = [torch.empty((self.n_real, ny, nx), dtype=torch.float64, device="cuda")
+               for _ in range(3)]
+        vlbm_moments(self.h, level, *out)
+        return out

@@ -1,0 +1,83 @@
+"""Host-side checks of the C ABI that need no GPU: the library loads, exports
+every function include/vlbm.h declares, and rejects invalid arguments before
+touching the device."""
+import ctypes
+
+import numpy as np
+import pytest
+
+from paper_2605_25282_amd import vlbm
+
+
+@pytest.fixture(scope="module")
+def lib():
+    return vlbm.lib()
+
+
+def test_header_declares_the_boundary():
+    names = vlbm.header_functions()
+    for required in ("vlbm_init_ensemble", "vlbm_step", "vlbm_moments", "vlbm_ensemble_stats",
+                     "vlbm_last_error", "vlbm_destroy"):
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol(lib):
+    missing = [n for n in vlbm.header_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_state_bytes(lib):
+    p = vlbm.Params.jet()
+    assert vlbm.vlbm_state_bytes(p, 128, 64, 8) == 20 * 8 * 128 * 64 * 8
+    pm = vlbm.Params.jet(precision="mixed")
+    plane = 128 * 64 * 8
+    f = (15 * plane * 4 + 255) // 256 * 256
+    assert vlbm.vlbm_state_bytes(pm, 128, 64, 8) == f + 5 * plane * 8
+
+
+@pytest.mark.parametrize("field,value", [("gamma", 1.0), ("alpha", 1.0), ("alpha", -0.1),
+                                         ("kappa", 0.5), ("pos_eps", 1.0), ("rho_amb", 0.0),
+                                         ("kl_modes", 65), ("kl_decay", -1), ("bc", 7),
+                                         ("limiter", 9), ("precision", 3), ("reserved", 1)])
+def test_invalid_params_rejected(lib, field, value):
+    p = vlbm.Params.jet()
+    setattr(p, field, value)
+    with pytest.raises(vlbm.VlbmError) as ei:
+        vlbm.vlbm_state_bytes(p, 16, 16, 1)
+    assert ei.value.code == vlbm.ERR_ARG
+    assert field.split("_")[0] in vlbm.last_error() or field == "reserved" or "jet constants" in vlbm.last_error()
+
+
+@pytest.mark.parametrize("nx,ny,R", [(2, 16, 1), (16, 2, 1), (16, 16, 0), (16, 16, 70000)])
+def test_invalid_sizes_rejected(lib, nx, ny, R):
+    with pytest.raises(vlbm.VlbmError) as ei:
+        vlbm.vlbm_state_bytes(vlbm.Params.jet(), nx, ny, R)
+    assert ei.value.code == vlbm.ERR_SIZE
+
+
+def test_init_rejects_before_any_device_work(lib):
+    """Validation happens before any HIP call, so these run without a GPU."""
+    p = vlbm.Params.jet()
+    lv = vlbm.Level(16, 16, 0.1, 0.0, (ctypes.c_void_p * 2)(None, None))
+    coefs = np.zeros((1, 20))
+    with pytest.raises(vlbm.VlbmError) as ei:
+        vlbm.vlbm_init_ensemble(p, [lv], coefs, 1, stream=type("S", (), {"cuda_stream": 0})())
+    assert ei.value.code == vlbm.ERR_ARG and "state" in vlbm.last_error()
+    lv = vlbm.Level(16, 16, 0.1, 0.0, (ctypes.c_void_p * 2)(4096, 8192))
+    bad = np.full((1, 20), 1.5)
+    with pytest.raises(vlbm.VlbmError) as ei:
+        vlbm.vlbm_init_ensemble(p, [lv], bad, 1, stream=type("S", (), {"cuda_stream": 0})())
+    assert ei.value.code == vlbm.ERR_ARG and "outside" in vlbm.last_error()
+    lv = vlbm.Level(16, 16, -0.1, 0.0, (ctypes.c_void_p * 2)(4096, 8192))
+    with pytest.raises(vlbm.VlbmError):
+        vlbm.vlbm_init_ensemble(p, [lv], coefs, 1, stream=type("S", (), {"cuda_stream": 0})())
+
+
+def test_null_handles_rejected(lib):
+    assert lib.vlbm_step(None, 1.0, 1, None) == vlbm.ERR_ARG
+    assert lib.vlbm_moments(None, 0, None, None, None) == vlbm.ERR_ARG
+    assert lib.vlbm_ensemble_stats(None, 0, 1, None, 0, None, 0) == vlbm.ERR_ARG
+    assert lib.vlbm_sort_samples(None, 1, 1, None) == vlbm.ERR_ARG
+    assert lib.vlbm_w1(None, None, 1, 1, None, None, None) == vlbm.ERR_ARG
+    assert lib.vlbm_stats_finalize(None, 1, 1, None, None, None) == vlbm.ERR_ARG
+    assert lib.vlbm_destroy(None) == vlbm.OK

@@ -1,0 +1,273 @@
+"""GPU parity of the HIP path against the CPU oracle, through the C ABI.
+
+Bar (FP64): per (variable, slot) plane, max |gpu - oracle| / max |oracle| <= 1e-11
+after the stated number of steps; the path is designed to be bitwise
+reproducible, so the tests also report the exact maximum difference.  The
+statistics are compared at 1e-3 relative (sums over cells of |difference| over
+sums of |reference|), and sort/W1 on seeded synthetic stores bit for bit / to
+rounding.  Every input is seeded; nothing the oracle consumes comes from the GPU.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import oracle as O
+from paper_2605_25282_amd import inputs, vlbm
+
+TOL = 1e-11
+
+
+def _to_oracle(gpu_state, m):
+    """[4 var][5 slot][R][ny][nx] -> oracle layout (20, ny, nx) for realization m."""
+    s = gpu_state[:, :, m]
+    return s.transpose(1, 0, 2, 3).reshape(20, s.shape[2], s.shape[3])
+
+
+def _plane_err(mine, ref):
+    """Relative error per (slot, var) plane (reading of the 1e-11 bar)."""
+    worst = 0.0
+    for s in range(5):
+        for v in range(4):
+            d = np.abs(mine[s * 4 + v] - ref[s * 4 + v]).max()
+            den = np.abs(ref[s * 4 + v]).max()
+            if den == 0.0:
+                den = np.abs(ref[s * 4 + 3]).max()
+            worst = max(worst, d / den)
+    return worst
+
+
+def _grid(name):
+    w = inputs.WORKLOADS[name]
+    return w, O.Grid(w.nx, w.ny, w.dx, w.y_min)
+
+
+def _oracle_runs(p, g, coefs, t_final, max_steps, ms):
+    out = {}
+    for m in ms:
+        out[m] = O.run(p, g, O.init(p, g, coefs[m]), t_final, max_steps=max_steps)
+    return out
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    vlbm.lib()
+    yield
+    torch.cuda.synchronize()
+
+
+def test_init_bitwise():
+    """Initial datum (eq:u0_def, correctly rounded inlet profile) and equilibrium
+    populations are bit-identical to the oracle's."""
+    w, g = _grid("jet128")
+    R = 8
+    coefs = inputs.kl_coefficients(inputs.DEFAULT_SEED, 0, R)
+    ens = vlbm.Ensemble(vlbm.Params.jet(), [(w.nx, w.ny, w.dx, w.y_min)], coefs, R)
+    st = ens.state(0).cpu().numpy()
+    ens.close()
+    p = O.Params()
+    for m in range(R):
+        ref = O.init(p, g, coefs[m])
+        assert np.array_equal(_to_oracle(st, m), ref), f"realization {m}"
+
+
+@pytest.mark.parametrize("alpha", [0.0, 1.0 / 3.0])
+def test_jet_50_steps(alpha):
+    """The headline parity case: 128 x 64 jet, 8 realizations, exactly 50 steps."""
+    w, g = _grid("jet128")
+    R, steps = 8, 50
+    coefs = inputs.kl_coefficients(inputs.DEFAULT_SEED, 0, R)
+    ens = vlbm.Ensemble(vlbm.Params.jet(alpha=alpha), [(w.nx, w.ny, w.dx, w.y_min)], coefs, R)
+    ens.step(1e30, steps)
+    st = ens.state(0).cpu().numpy()
+    t, s, a, status = ens.times(0)
+    ens.close()
+    assert np.all(s == steps) and np.all(status == 0)
+    p = O.Params(alpha=alpha)
+    ref = _oracle_runs(p, g, coefs, 1e30, steps, range(R))
+    worst, maxdiff = 0.0, 0.0
+    for m in range(R):
+        r_st, r_t, r_n, r_a, rc = ref[m]
+        assert rc == O.OK and r_n == steps
+        mine = _to_oracle(st, m)
+        worst = max(worst, _plane_err(mine, r_st))
+        maxdiff = max(maxdiff, np.abs(mine - r_st).max())
+        assert t[m] == r_t and a[m] == r_a
+    print(f"alpha={alpha}: worst plane rel err {worst:.3e}, max abs diff {maxdiff:.3e}")
+    assert worst <= TOL
+
+
+def test_jet_to_t_final():
+    """A full run to t = 1e-4: identical step counts, final times and states."""
+    w, g = _grid("jet128")
+    R = 8
+    coefs = inputs.kl_coefficients(inputs.DEFAULT_SEED, 100, R)
+    ens = vlbm.Ensemble(vlbm.Params.jet(), [(w.nx, w.ny, w.dx, w.y_min)], coefs, R)
+    ens.run(w.t_final, chunk=16)
+    st = ens.state(0).cpu().numpy()
+    t, s, a, status = ens.times(0)
+    ens.close()
+    ref = _oracle_runs(O.Params(), g, coefs, w.t_final, 1 << 30, range(R))
+    for m in range(R):
+        r_st, r_t, r_n, r_a, rc = ref[m]
+        assert s[m] == r_n and t[m] == r_t == w.t_final and a[m] == r_a
+        assert _plane_err(_to_oracle(st, m), r_st) <= TOL
+
+
+def _prim(rho, v1, v2, p, gamma):
+    return np.stack([rho, rho * v1, rho * v2, p / (gamma - 1.0) + 0.5 * rho * (v1 * v1 + v2 * v2)])
+
+
+@pytest.mark.parametrize("bc,lim", [("periodic", "limiter"), ("periodic", "zero"), ("periodic", "one"),
+                                    ("neumann", "limiter")])
+def test_verification_modes(bc, lim):
+    """Other boundary/theta modes on a loaded smooth or shock-tube state, 30 steps."""
+    nx, ny, R, gamma = 70, 37, 3, 1.4
+    dx = 1.0 / nx
+    y, x = np.meshgrid(np.arange(ny), np.arange(nx), indexing="ij")
+    u = np.zeros((4, R, ny, nx))
+    for m in range(R):
+        if bc == "periodic":
+            rho = 1.3 + 0.3 * np.sin(2 * np.pi * (x / nx + m / 7.0)) * np.cos(2 * np.pi * y / ny)
+            v1 = 0.5 * np.cos(2 * np.pi * y / ny)
+            v2 = 0.3 * np.sin(2 * np.pi * x / nx)
+            pr = 1.0 + 0.2 * np.cos(2 * np.pi * (x / nx + y / ny))
+        else:
+            left = x < nx // 2 + m
+            rho = np.where(left, 1.0, 0.125)
+            v1 = np.zeros_like(rho)
+            v2 = np.zeros_like(rho)
+            pr = np.where(left, 1.0, 0.1)
+        u[:, m] = _prim(rho, v1, v2, pr, gamma)
+    prm = vlbm.Params.jet(gamma=gamma, bc=bc, limiter=lim, kl_modes=0)
+    ens = vlbm.Ensemble(prm, [(nx, ny, dx, 0.0)], None, R)
+    ens.set_macroscopic(0, torch.tensor(u, device="cuda"))
+    ens.step(1e30, 30)
+    st = ens.state(0).cpu().numpy()
+    ens.close()
+    p = O.Params(gamma=gamma, bc=bc, theta_mode=lim, kl_modes=0)
+    g = O.Grid(nx, ny, dx, 0.0)
+    for m in range(R):
+        ref, _, n, _, rc = O.run(p, g, O.from_macroscopic(p, g, u[:, m]), 1e30, max_steps=30)
+        assert n == 30
+        assert _plane_err(_to_oracle(st, m), ref) <= TOL
+
+
+def test_moments_bitwise():
+    w, g = _grid("jet128")
+    R = 4
+    coefs = inputs.kl_coefficients(inputs.DEFAULT_SEED, 0, R)
+    ens = vlbm.Ensemble(vlbm.Params.jet(), [(w.nx, w.ny, w.dx, w.y_min)], coefs, R)
+    ens.step(1e30, 12)
+    rho, speed, pr = [t.cpu().numpy() for t in ens.moments(0)]
+    ens.close()
+    p = O.Params()
+    for m in range(R):
+        ref, *_ = O.run(p, g, O.init(p, g, coefs[m]), 1e30, max_steps=12)
+        r, s, q = O.moments(p, ref[0:4])
+        assert np.array_equal(rho[m], r) and np.array_equal(speed[m], s) and np.array_equal(pr[m], q)
+
+
+def _rel_l1(a, b):
+    return np.abs(a - b).sum() / np.abs(b).sum()
+
+
+def test_two_level_statistics():
+    """Mean, std (r = 1 and r = 2) and the one-point W1 between a fine and a coarse
+    level restricted to the coarse grid, against the oracle's own runs."""
+    R = 8
+    fine, coarse = (128, 64), (64, 32)
+    coefs = inputs.kl_coefficients(inputs.DEFAULT_SEED, 0, R)
+    t_final = 1e-4
+    levels = [(nx, ny, 1.0 / nx, -0.25) for (nx, ny) in (coarse, fine)]
+    ens = vlbm.Ensemble(vlbm.Params.jet(), levels, coefs, R)
+    ens.run(t_final, chunk=16)
+    ncell = coarse[0] * coarse[1]
+    accs, samples = [], []
+    for lvl, r in ((0, 1), (1, 2)):
+        acc = torch.empty((3, 2, ncell), dtype=torch.float64, device="cuda")
+        smp = torch.empty((R, ncell), dtype=torch.float64, device="cuda")
+        vlbm.vlbm_ensemble_stats(ens.h, lvl, r, acc, 0, smp, 0)
+        accs.append(acc)
+        samples.append(smp)
+    mean = torch.empty((3, ncell), dtype=torch.float64, device="cuda")
+    std = torch.empty_like(mean)
+    vlbm.vlbm_stats_finalize(accs[1], ncell, R, mean, std)
+    for smp in samples:
+        vlbm.vlbm_sort_samples(smp, ncell, R)
+    w1c = torch.empty(ncell, dtype=torch.float64, device="cuda")
+    w1m = torch.empty(1, dtype=torch.float64, device="cuda")
+    vlbm.vlbm_w1(samples[0], samples[1], ncell, R, w1c, w1m)
+    torch.cuda.synchronize()
+    mean, std, w1c, w1m = mean.cpu().numpy(), std.cpu().numpy(), w1c.cpu().numpy(), w1m.item()
+    ens.close()
+    # oracle
+    p = O.Params()
+    fields = {}
+    for (nx, ny), r in ((coarse, 1), (fine, 2)):
+        g = O.Grid(nx, ny, 1.0 / nx, -0.25)
+        st = np.stack([O.run(p, g, O.init(p, g, coefs[m]), t_final)[0] for m in range(R)])
+        rho, sp, pr = O.moments(p, st[:, 0:4])
+        fields[r] = [O.restrict(f, r) for f in (rho, sp, pr)]
+    for f in range(3):
+        assert _rel_l1(mean[f], O.ensemble_mean(fields[2][f]).ravel()) <= 1e-12
+        assert _rel_l1(std[f], O.ensemble_std(fields[2][f]).ravel()) <= 1e-9
+    ref_w1 = O.w1(fields[1][0], fields[2][0]).ravel()
+    assert _rel_l1(w1c, ref_w1) <= 1e-12
+    assert w1m == pytest.approx(ref_w1.mean(), rel=1e-12)
+
+
+@pytest.mark.parametrize("m,ncell", [(1, 5), (7, 300), (64, 1000), (100, 333), (1000, 77), (4096, 3)])
+def test_sort_and_w1_synthetic(m, ncell):
+    a = inputs.random_fields(1000 + m, (m, ncell))
+    b = inputs.random_fields(2000 + m, (m, ncell))
+    ta, tb = torch.tensor(a, device="cuda"), torch.tensor(b, device="cuda")
+    vlbm.vlbm_sort_samples(ta, ncell, m)
+    vlbm.vlbm_sort_samples(tb, ncell, m)
+    w1c = torch.empty(ncell, dtype=torch.float64, device="cuda")
+    vlbm.vlbm_w1(ta, tb, ncell, m, w1c, None)
+    torch.cuda.synchronize()
+    assert np.array_equal(ta.cpu().numpy(), np.sort(a, axis=0))
+    assert np.allclose(w1c.cpu().numpy(), O.w1(a, b), rtol=1e-12, atol=0)
+
+
+def test_nonpositive_state_is_reported():
+    """A loaded state with negative pressure latches the realization's status and
+    vlbm_step reports VLBM_ERR_NONPOSITIVE; the other realization is unaffected."""
+    nx, ny, R, gamma = 16, 16, 2, 1.4
+    one = np.ones((ny, nx))
+    u = np.zeros((4, R, ny, nx))
+    u[:, 0] = _prim(one, 0 * one, 0 * one, one, gamma)
+    bad = one.copy()
+    bad[5, 7] = -1.0
+    u[:, 1] = _prim(one, 0 * one, 0 * one, bad, gamma)
+    ens = vlbm.Ensemble(vlbm.Params.jet(gamma=gamma, bc="neumann", kl_modes=0), [(nx, ny, 0.1, 0.0)], None, R)
+    ens.set_macroscopic(0, torch.tensor(u, device="cuda"))
+    with pytest.raises(vlbm.VlbmError) as ei:
+        ens.step(1.0, 3)
+    assert ei.value.code == vlbm.ERR_NONPOSITIVE
+    t, s, a, status = ens.times(0)
+    ens.close()
+    assert status[0] == 0 and status[1] == vlbm.ERR_NONPOSITIVE
+
+
+def test_jet640_sampled_realizations():
+    """Full-size 640 x 320 ensemble of 64 realizations in one launch configuration,
+    50 steps; three realizations recomputed by the oracle."""
+    w, g = _grid("jet640")
+    steps = 50
+    coefs = inputs.kl_coefficients(inputs.DEFAULT_SEED, 0, w.m)
+    ens = vlbm.Ensemble(vlbm.Params.jet(), [(w.nx, w.ny, w.dx, w.y_min)], coefs, w.m)
+    ens.step(1e30, steps)
+    st = ens.state(0)
+    picks = (0, 37, w.m - 1)
+    mine = {m: st[:, :, m].cpu().numpy() for m in picks}
+    ens.close()
+    del st
+    ref = _oracle_runs(O.Params(), g, coefs, 1e30, steps, picks)
+    for m in picks:
+        s = mine[m]
+        assert _plane_err(s.transpose(1, 0, 2, 3).reshape(20, w.ny, w.nx), ref[m][0]) <= TOL
