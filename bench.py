@@ -1,0 +1,226 @@
+"""Benchmark of the VLBM Mach-2000 jet ensemble hot path on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--precision fp64|mixed]
+
+One benchmark step is one pass of the whole hot path over one ensemble of
+synthetic realizations of the jet workload (640 x 320 nodes, M = 64, to
+t = 1e-3): initial datum, time stepping (fused collide-stream kernel with the
+kinetic-speed reduction and boundary layers), moments, conservative
+restriction, ensemble mean and standard deviation of (rho, |v|, p), the
+restricted density samples, their per-cell sort, and the one-point W1 against
+the previous step's sorted store (identical seeds: W1 must be exactly 0, a
+run-to-run determinism check).
+
+Prints one JSON line.  `value` is ensemble GLUPS: node updates summed over
+realizations per second of the whole step.  `roofline` reports the step
+kernel: algorithmic 320 B per FP64 node update (200 B mixed) over its average
+launch duration, measured with HIP events on the stream the kernels run on.
+`cpu_baseline` times the CPU oracle on a bounded sample on this host.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "ensemble GLUPS (cell-updates/s summed over realizations) + % HBM roofline, FP64 vs mixed"
+HBM_PEAK_GBS = 8000.0
+BYTES_PER_LUP = {"fp64": 320.0, "mixed": 200.0}
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in sorted(os.listdir(os.path.join(ROOT, "paper_2605_25282_amd", "csrc"))):
+        with open(os.path.join(ROOT, "paper_2605_25282_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(precision: str):
+    """HBM bytes per launch of the step kernel from the committed rocprofv3
+    counter summary, if it was taken on the current kernel sources."""
+    path = os.path.join(ROOT, "profiles", f"traffic_step_jet640_{precision}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        d = json.load(f)
+    if d.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    return d.get("bytes_per_launch")
+
+
+def cpu_baseline(workload, seconds_target: float = 15.0):
+    """The oracle, as it stands, on a bounded sample of the same workload: the first
+    realizations of the ensemble on the full grid for a fixed number of steps."""
+    import numpy as np
+
+    import oracle as O
+    from paper_2605_25282_amd import inputs
+
+    threads = min(8, os.cpu_count() or 1)
+    p = O.Params()
+    g = O.Grid(workload.nx, workload.ny, workload.dx, workload.y_min)
+    coefs = inputs.kl_coefficients(inputs.DEFAULT_SEED, 0, threads)
+    # size the sample from a short probe so that it takes ~seconds_target
+    t0 = time.perf_counter()
+    O.run(p, g, O.init(p, g, coefs[0]), 1e30, max_steps=2)
+    per_step = (time.perf_counter() - t0) / 2
+    steps = int(max(4, min(200, seconds_target / max(per_step, 1e-6))))
+    t0 = time.perf_counter()
+    states, t, n, status = O.run_ensemble(p, g, coefs, 1e30, max_steps=steps, threads=threads)
+    el = time.perf_counter() - t0
+    lups = float(n.sum()) * workload.nx * workload.ny
+    return {"value": lups / el / 1e9, "unit": "GLUPS", "cores": threads, "kind": "oracle",
+            "sample": f"{threads} realizations x {steps} steps of the {workload.nx}x{workload.ny} "
+                      f"jet on {threads} host threads ({el:.1f} s, {lups:.3e} node updates)"}
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
+    ap.add_argument("--workload", default="jet640")
+    ap.add_argument("--chunk", type=int, default=240, help="launches per vlbm_step call")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also run one device copy of known size (counter calibration)")
+    ap.add_argument("--profile-launches", type=int, default=0,
+                    help="profiling mode: initial datum, this many step launches and a "
+                         "2 GiB device copy, no statistics and no JSON line")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; multi-GPU runs are not "
+                                   "supported (--gpus must be 1)"}))
+        return 2
+
+    import numpy as np
+    import torch
+
+    from paper_2605_25282_amd import inputs, vlbm
+
+    if not torch.cuda.is_available():
+        print(json.dumps({"error": "no GPU visible"}))
+        return 2
+    vlbm.lib()  # fails loudly if the HIP library was not built
+    w = inputs.WORKLOADS[args.workload]
+    R, r_stats, r_w1 = w.m, 1, 2
+    params = vlbm.Params.jet(precision=args.precision)
+    coefs = inputs.kl_coefficients(inputs.DEFAULT_SEED, 0, R)
+    stream = torch.cuda.current_stream()
+    ncell = w.nx * w.ny
+    ncell_w1 = (w.nx // r_w1) * (w.ny // r_w1)
+    acc = torch.empty((3, 2, ncell), dtype=torch.float64, device="cuda")
+    mean = torch.empty((3, ncell), dtype=torch.float64, device="cuda")
+    std = torch.empty_like(mean)
+    sacc = torch.empty((3, 2, ncell_w1), dtype=torch.float64, device="cuda")
+    samples = [torch.empty((R, ncell_w1), dtype=torch.float64, device="cuda") for _ in range(2)]
+    w1c = torch.empty(ncell_w1, dtype=torch.float64, device="cuda")
+    w1m = torch.zeros(1, dtype=torch.float64, device="cuda")
+    # the ensemble's state buffers are allocated once and reused by every step
+    nbytes = vlbm.vlbm_state_bytes(params, w.nx, w.ny, R)
+    bufs = [torch.empty(nbytes, dtype=torch.uint8, device="cuda") for _ in range(2)]
+    level = vlbm.Level(w.nx, w.ny, w.dx, w.y_min,
+                       (vlbm._VP * 2)(bufs[0].data_ptr(), bufs[1].data_ptr()))
+
+    if args.profile_launches > 0:
+        h = vlbm.vlbm_init_ensemble(params, [level], coefs, R, stream)
+        vlbm.vlbm_step(h, w.t_final, args.profile_launches, want_done=True)
+        vlbm.vlbm_destroy(h)
+        a = torch.ones(1 << 28, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        print(f"profiled {args.profile_launches} step launches of {w.name} "
+              f"({R} x {w.nx} x {w.ny}) and one 2 GiB copy", flush=True)
+        return 0
+
+    step_ms, step_launches = [0.0], [0]
+    totals = {"lups": 0.0}
+
+    def one_step(k: int, timed: bool):
+        h = vlbm.vlbm_init_ensemble(params, [level], coefs, R, stream)
+        done = False
+        while not done:
+            if timed:
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+            done = vlbm.vlbm_step(h, w.t_final, args.chunk, want_done=True)
+            if timed:
+                e1.record(stream)
+                e1.synchronize()
+                step_ms[0] += e0.elapsed_time(e1)
+                step_launches[0] += args.chunk
+        t, s, a, status = vlbm.vlbm_times(h, 0, R)
+        vlbm.vlbm_ensemble_stats(h, 0, r_stats, acc, 0, None, 0)
+        vlbm.vlbm_stats_finalize(acc, ncell, R, mean, std, stream)
+        cur, prev = samples[k % 2], samples[(k + 1) % 2]
+        vlbm.vlbm_ensemble_stats(h, 0, r_w1, sacc, 0, cur, 0)
+        vlbm.vlbm_sort_samples(cur, ncell_w1, R, stream)
+        if k > 0:
+            vlbm.vlbm_w1(cur, prev, ncell_w1, R, w1c, w1m, stream)
+        vlbm.vlbm_destroy(h)
+        if timed:
+            totals["lups"] += float(s.sum()) * w.nx * w.ny
+        return s, t
+
+    for k in range(args.warmup):
+        one_step(k, False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    last_steps = None
+    for k in range(args.steps):
+        last_steps, t_end = one_step(args.warmup + k, True)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+
+    w1_check = float(w1m.item()) if args.warmup + args.steps > 1 else None
+    value = totals["lups"] / elapsed / 1e9
+    # Step-kernel roofline: launches in the timed chunks (graph or eager) vs events.
+    lup_per_step_pass = float(last_steps.sum()) * w.nx * w.ny
+    launches_per_pass = step_launches[0] / max(args.steps, 1)
+    avg_launch_ms = step_ms[0] / max(step_launches[0], 1)
+    bytes_pass = BYTES_PER_LUP[args.precision] * lup_per_step_pass
+    achieved = bytes_pass / (step_ms[0] / args.steps / 1e3) / 1e9
+    traffic = measured_traffic(args.precision)
+    if args.copy_probe:
+        a = torch.empty(1 << 28, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+    out = {
+        "metric": METRIC, "value": round(value, 4), "unit": "GLUPS", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(elapsed / args.steps * 1e3, 3), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64" if args.precision == "fp64" else "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": f"{w.name}: Mach-2000 jet, {w.nx}x{w.ny} nodes on [0,1]x[-0.25,0.25], "
+                               f"M={R} realizations to t={w.t_final:g}, {args.precision}",
+                   "precision": args.precision, "nx": w.nx, "ny": w.ny, "realizations": R,
+                   "t_final": w.t_final, "seed": inputs.DEFAULT_SEED,
+                   "time_steps_per_realization": [int(last_steps.min()), int(last_steps.max())]},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": traffic,
+                     "kernel": "vlbm step kernel", "bytes_per_node_update": BYTES_PER_LUP[args.precision],
+                     "avg_launch_ms": round(avg_launch_ms, 5),
+                     "launches_per_pass": launches_per_pass},
+        "w1_rerun": w1_check,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(w)
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())
