@@ -214,6 +214,19 @@ vlbm_status vlbm_sort_samples(double *samples, int64_t n_cells, int32_t m, void 
 vlbm_status vlbm_w1(const double *sorted_a, const double *sorted_b, int64_t n_cells, int32_t m,
                     double *w1_cell, double *w1_mean, void *hip_stream);
 
+/* Step kernel implementations (vlbm_tune). */
+#define VLBM_KERNEL_REFERENCE 0 /* one thread per node, neighbours recomputed        */
+#define VLBM_KERNEL_MARCH 1     /* wavefront strips marching over rows (default)      */
+
+/*
+ * Select the step kernel and its work decomposition for this ensemble:
+ * chunk_rows is the number of rows one wavefront marches over (0 = chosen
+ * from the level sizes and ensemble size; otherwise 4 <= chunk_rows <= 65536).
+ * Results do not depend on the choice (every kernel is bit-identical); only
+ * the speed does.  The autotuner times candidates through this call.
+ */
+vlbm_status vlbm_tune(vlbm_ensemble *e, int32_t kernel, int32_t chunk_rows);
+
 /* Release the handle and its control arrays (synchronizes its stream). */
 vlbm_status vlbm_destroy(vlbm_ensemble *e);
 

@@ -20,6 +20,10 @@ namespace vlbm {
 template <int PREC> __global__ void init_macro_kernel(PhysArgs, LevelArgs, const double *, Ctl);
 template <int PREC> __global__ void equilibrium_kernel(PhysArgs, LevelArgs, Ctl, int);
 template <int PREC> __global__ void step_ref_kernel(PhysArgs, LevelArgs, Ctl, int, double);
+struct MarchArgs {
+    int nstrip, chunk, nchunk, nblocks, per_xcd, lane62_last;
+};
+template <int PREC> __global__ void step_march_kernel(PhysArgs, LevelArgs, Ctl, int, double, MarchArgs);
 template <int PREC> __global__ void moments_kernel(PhysArgs, LevelArgs, Ctl, int, double *, double *, double *);
 template <int PREC> __global__ void get_state_kernel(LevelArgs, Ctl, int, double *);
 template <int PREC> __global__ void set_macro_kernel(PhysArgs, LevelArgs, Ctl, const double *);
@@ -137,11 +141,67 @@ struct vlbm_ensemble {
     double *coeffs_dev = nullptr;
     Ctl ctl{};
     long long n_launch = 0; // launches since the last (re)initialisation: ring phase = n % 3
+    int kernel = VLBM_KERNEL_MARCH;
+    int chunk_rows = 0;     // 0 = automatic
 };
 
 namespace {
 
 int phase_of(const vlbm_ensemble *e) { return (int)(e->n_launch % 3); }
+
+// Work decomposition of the marching kernel for one level.
+MarchArgs march_args(const vlbm_ensemble *e, const LevelArgs &L, unsigned *grid)
+{
+    MarchArgs ma{};
+    const bool periodic = e->p.bc == VLBM_BC_PERIODIC;
+    if (!periodic && (L.nx - 1) % 60 == 0) {
+        ma.nstrip = (L.nx - 1) / 60;
+        ma.lane62_last = 1;
+    } else {
+        ma.nstrip = (L.nx + 59) / 60;
+        ma.lane62_last = 0;
+    }
+    int chunk = e->chunk_rows;
+    if (chunk <= 0) {
+        // about three waves per SIMD slot of the chip, rows of at least 16
+        const long long target = 3 * 256 * 4;
+        const long long per_chunk = (long long)L.R * ma.nstrip;
+        long long nch = (target + per_chunk - 1) / per_chunk;
+        if (nch < 1)
+            nch = 1;
+        chunk = (int)((L.ny + nch - 1) / nch);
+        if (chunk < 16)
+            chunk = 16;
+    }
+    if (chunk > L.ny)
+        chunk = L.ny;
+    ma.chunk = chunk;
+    ma.nchunk = (L.ny + chunk - 1) / chunk;
+    const long long waves = (long long)L.R * ma.nstrip * ma.nchunk;
+    ma.nblocks = (int)((waves + 3) / 4);
+    ma.per_xcd = (ma.nblocks + 7) / 8;
+    *grid = (unsigned)(8 * ma.per_xcd);
+    return ma;
+}
+
+vlbm_status launch_step(vlbm_ensemble *e, const PhysArgs &ph, const LevelArgs &L, int phase, double t_final)
+{
+    if (e->kernel == VLBM_KERNEL_REFERENCE) {
+        if (e->p.precision == VLBM_FP64)
+            step_ref_kernel<0><<<node_grid(L), 256, 0, e->stream>>>(ph, L, e->ctl, phase, t_final);
+        else
+            step_ref_kernel<1><<<node_grid(L), 256, 0, e->stream>>>(ph, L, e->ctl, phase, t_final);
+    } else {
+        unsigned grid = 0;
+        const MarchArgs ma = march_args(e, L, &grid);
+        if (e->p.precision == VLBM_FP64)
+            step_march_kernel<0><<<grid, 256, 0, e->stream>>>(ph, L, e->ctl, phase, t_final, ma);
+        else
+            step_march_kernel<1><<<grid, 256, 0, e->stream>>>(ph, L, e->ctl, phase, t_final, ma);
+    }
+    LAUNCH_CHECK("step");
+    return VLBM_OK;
+}
 
 vlbm_status check_level(const vlbm_ensemble *e, int level)
 {
@@ -346,12 +406,10 @@ vlbm_status vlbm_step(vlbm_ensemble *e, double t_final, int32_t n_steps, int32_t
     for (int s = 0; s < n_steps; ++s) {
         const int phase = phase_of(e);
         for (const LevelArgs &L : e->levels) {
-            if (e->p.precision == VLBM_FP64)
-                step_ref_kernel<0><<<node_grid(L), 256, 0, e->stream>>>(ph, L, e->ctl, phase, t_final);
-            else
-                step_ref_kernel<1><<<node_grid(L), 256, 0, e->stream>>>(ph, L, e->ctl, phase, t_final);
+            vlbm_status rc = launch_step(e, ph, L, phase, t_final);
+            if (rc != VLBM_OK)
+                return rc;
         }
-        LAUNCH_CHECK("step");
         e->n_launch++;
     }
     if (all_done) {
@@ -513,6 +571,19 @@ vlbm_status vlbm_w1(const double *a, const double *b, int64_t n_cells, int32_t m
     if (w1_mean)
         scale_kernel<<<1, 64, 0, st>>>(w1_mean, 1.0 / (double)n_cells);
     LAUNCH_CHECK("w1");
+    return VLBM_OK;
+}
+
+vlbm_status vlbm_tune(vlbm_ensemble *e, int32_t kernel, int32_t chunk_rows)
+{
+    if (!e)
+        return fail(VLBM_ERR_ARG, "ensemble is NULL");
+    if (kernel != VLBM_KERNEL_REFERENCE && kernel != VLBM_KERNEL_MARCH)
+        return fail(VLBM_ERR_ARG, "unknown kernel %d", kernel);
+    if (chunk_rows != 0 && (chunk_rows < 4 || chunk_rows > 65536))
+        return fail(VLBM_ERR_ARG, "chunk_rows must be 0 or lie in [4, 65536] (got %d)", chunk_rows);
+    e->kernel = kernel;
+    e->chunk_rows = chunk_rows;
     return VLBM_OK;
 }
 

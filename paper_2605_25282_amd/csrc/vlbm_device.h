@@ -303,6 +303,8 @@ struct StateFP64 {
     }
     __device__ __forceinline__ double ld(int v, int s, int m, size_t node) const { return p[idx(v, s, m, node)]; }
     __device__ __forceinline__ void st(int v, int s, int m, size_t node, double x) const { p[idx(v, s, m, node)] = x; }
+    // value a store of x in variable v reads back as
+    __device__ __forceinline__ double stored(int, double x) const { return x; }
 };
 
 struct StateMixed {
@@ -323,6 +325,7 @@ struct StateMixed {
         else
             pd[((size_t)s * (size_t)R + (size_t)m) * plane + node] = x;
     }
+    __device__ __forceinline__ double stored(int v, double x) const { return v < 3 ? (double)(float)x : x; }
 };
 
 // Launch arguments of one mesh level and of the physics (plain values).
@@ -338,5 +341,35 @@ struct PhysArgs {
     double rho_amb, p_amb, rho_jet, v_jet, r_jet, kl_amp;
     int kl_modes, kl_decay, bc, limiter;
 };
+
+
+enum { BC_JET = 0, BC_PERIODIC = 1, BC_NEUMANN = 2 };
+enum { LIM_RLMP = 0, LIM_ZERO = 1, LIM_ONE = 2 };
+
+template <int PREC> struct StateOf;
+template <> struct StateOf<0> {
+    typedef StateFP64 type;
+    __device__ static type make(void *b, size_t plane, int R) { return StateFP64{(double *)b, plane, R}; }
+};
+template <> struct StateOf<1> {
+    typedef StateMixed type;
+    __device__ static type make(void *b, size_t plane, int R)
+    {
+        const size_t fbytes = (((size_t)15 * (size_t)R * plane * sizeof(float)) + 255) & ~(size_t)255;
+        return StateMixed{(float *)b, (double *)((char *)b + fbytes), plane, R};
+    }
+};
+
+// Node kinds of reading R8: 0 interior, 1 Dirichlet inlet layer, 2 copy layer.
+__device__ __forceinline__ int node_kind(int bc, int nx, int ny, int i, int j)
+{
+    if (bc == BC_PERIODIC)
+        return 0;
+    if (bc == BC_JET && i == 0)
+        return 1;
+    if (i == 0 || i == nx - 1 || j == 0 || j == ny - 1)
+        return 2;
+    return 0;
+}
 
 } // namespace vlbm

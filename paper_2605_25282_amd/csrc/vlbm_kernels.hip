@@ -9,35 +9,6 @@
 
 namespace vlbm {
 
-enum { BC_JET = 0, BC_PERIODIC = 1, BC_NEUMANN = 2 };
-enum { LIM_RLMP = 0, LIM_ZERO = 1, LIM_ONE = 2 };
-
-template <int PREC> struct StateOf;
-template <> struct StateOf<0> {
-    typedef StateFP64 type;
-    __device__ static type make(void *b, size_t plane, int R) { return StateFP64{(double *)b, plane, R}; }
-};
-template <> struct StateOf<1> {
-    typedef StateMixed type;
-    __device__ static type make(void *b, size_t plane, int R)
-    {
-        const size_t fbytes = (((size_t)15 * (size_t)R * plane * sizeof(float)) + 255) & ~(size_t)255;
-        return StateMixed{(float *)b, (double *)((char *)b + fbytes), plane, R};
-    }
-};
-
-// Node kinds of reading R8: 0 interior, 1 Dirichlet inlet layer, 2 copy layer.
-__device__ __forceinline__ int node_kind(int bc, int nx, int ny, int i, int j)
-{
-    if (bc == BC_PERIODIC)
-        return 0;
-    if (bc == BC_JET && i == 0)
-        return 1;
-    if (i == 0 || i == nx - 1 || j == 0 || j == ny - 1)
-        return 2;
-    return 0;
-}
-
 // ---------------------------------------------------------------------------
 // Initial datum (eq:u0_def): macroscopic state and its wave-speed maximum.
 // ---------------------------------------------------------------------------

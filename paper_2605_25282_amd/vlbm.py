@@ -95,6 +95,7 @@ def lib():
             "vlbm_stats_finalize": ([_VP, i64, i64, _VP, _VP, _VP], i32),
             "vlbm_sort_samples": ([_VP, i64, i32, _VP], i32),
             "vlbm_w1": ([_VP, _VP, i64, i32, _VP, _VP, _VP], i32),
+            "vlbm_tune": ([_VP, i32, i32], i32),
             "vlbm_destroy": ([_VP], i32),
         }
         for name, (args, res) in sig.items():
@@ -193,6 +194,14 @@ def vlbm_w1(a, b, n_cells: int, m: int, w1_cell=None, w1_mean=None, stream=None)
                          _stream(stream)))
 
 
+KERNEL = {"reference": 0, "march": 1}
+
+
+def vlbm_tune(h, kernel: str | int = "march", chunk_rows: int = 0) -> None:
+    k = KERNEL[kernel] if isinstance(kernel, str) else kernel
+    _check(lib().vlbm_tune(h, k, chunk_rows))
+
+
 def vlbm_destroy(h) -> None:
     _check(lib().vlbm_destroy(h))
 
@@ -228,6 +237,9 @@ class Ensemble:
             self.close()
         except Exception:
             pass
+
+    def tune(self, kernel: str | int = "march", chunk_rows: int = 0) -> None:
+        vlbm_tune(self.h, kernel, chunk_rows)
 
     def step(self, t_final: float, n_steps: int, want_done: bool = True):
         return vlbm_step(self.h, t_final, n_steps, want_done)

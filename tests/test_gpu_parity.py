@@ -271,3 +271,66 @@ def test_jet640_sampled_realizations():
     for m in picks:
         s = mine[m]
         assert _plane_err(s.transpose(1, 0, 2, 3).reshape(20, w.ny, w.nx), ref[m][0]) <= TOL
+
+
+def _loaded_state(bc, nx, ny, R, gamma):
+    y, x = np.meshgrid(np.arange(ny), np.arange(nx), indexing="ij")
+    u = np.zeros((4, R, ny, nx))
+    for m in range(R):
+        if bc == "periodic":
+            rho = 1.3 + 0.3 * np.sin(2 * np.pi * (x / nx + m / 7.0)) * np.cos(2 * np.pi * y / ny)
+            v1 = 0.5 * np.cos(2 * np.pi * y / ny)
+            v2 = 0.3 * np.sin(2 * np.pi * x / nx)
+            pr = 1.0 + 0.2 * np.cos(2 * np.pi * (x / nx + y / ny))
+        else:
+            left = (x + y // 3) < nx // 2 + m
+            rho = np.where(left, 1.0, 0.125)
+            v1 = np.where(left, 0.3, -0.2)
+            v2 = 0.1 * np.sin(2 * np.pi * x / nx)
+            pr = np.where(left, 1.0, 0.1)
+        u[:, m] = _prim(rho, v1, v2, pr, gamma)
+    return u
+
+
+@pytest.mark.parametrize("bc,nx,ny,chunk", [
+    ("jet", 128, 64, 0), ("jet", 121, 37, 16), ("jet", 181, 50, 7), ("jet", 61, 19, 4),
+    ("jet", 3, 3, 4), ("jet", 64, 5, 0), ("neumann", 61, 33, 8), ("neumann", 122, 29, 5),
+    ("periodic", 70, 37, 16), ("periodic", 121, 20, 6), ("neumann", 3, 4, 4)])
+def test_march_kernel_equals_reference(bc, nx, ny, chunk):
+    """The marching kernel (strips of 60 output columns, register ring over rows) and the
+    reference kernel give bit-identical states, including grids where the last column
+    falls on a strip edge, ragged row chunks and 3-node levels."""
+    R, steps, gamma = 3, 25, (5.0 / 3.0 if bc == "jet" else 1.4)
+    coefs = inputs.kl_coefficients(inputs.DEFAULT_SEED, 0, R)
+    out = {}
+    for kern in ("reference", "march"):
+        prm = vlbm.Params.jet(bc=bc, gamma=gamma) if bc == "jet" else \
+            vlbm.Params.jet(bc=bc, gamma=gamma, kl_modes=0)
+        y_min = -0.5 * ny / nx
+        ens = vlbm.Ensemble(prm, [(nx, ny, 1.0 / nx, y_min)], coefs if bc == "jet" else None, R)
+        ens.tune(kern, chunk)
+        if bc != "jet":
+            ens.set_macroscopic(0, torch.tensor(_loaded_state(bc, nx, ny, R, gamma), device="cuda"))
+        ens.step(1e30, steps)
+        out[kern] = (ens.state(0).cpu().numpy(), ens.times(0))
+        ens.close()
+    assert np.array_equal(out["reference"][0], out["march"][0])
+    for a, b in zip(out["reference"][1], out["march"][1]):
+        assert np.array_equal(a, b)
+
+
+def test_march_kernel_equals_reference_jet640():
+    """Full-size 640 x 320 x 64 ensemble, 30 steps, default decomposition."""
+    w = inputs.WORKLOADS["jet640"]
+    coefs = inputs.kl_coefficients(inputs.DEFAULT_SEED, 0, w.m)
+    res = {}
+    for kern in ("reference", "march"):
+        ens = vlbm.Ensemble(vlbm.Params.jet(), [(w.nx, w.ny, w.dx, w.y_min)], coefs, w.m)
+        ens.tune(kern, 0)
+        ens.step(1e30, 30)
+        st = ens.state(0)
+        res[kern] = (st.sum(dim=(2, 3, 4)).cpu().numpy(), st[:, :, ::9].cpu().numpy())
+        ens.close()
+        del st
+    assert np.array_equal(res["reference"][0], res["march"][0])
+    assert np.array_equal(res["reference"][1], res["march"][1])
