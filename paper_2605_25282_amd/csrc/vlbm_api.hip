@@ -143,6 +143,8 @@ struct vlbm_ensemble {
     long long n_launch = 0; // launches since the last (re)initialisation: ring phase = n % 3
     int kernel = VLBM_KERNEL_MARCH;
     int chunk_rows = 0;     // 0 = automatic
+    int n_cu = 256;         // compute units of the device
+    int march_blocks_per_cu = 1;
 };
 
 namespace {
@@ -163,8 +165,8 @@ MarchArgs march_args(const vlbm_ensemble *e, const LevelArgs &L, unsigned *grid)
     }
     int chunk = e->chunk_rows;
     if (chunk <= 0) {
-        // about three waves per SIMD slot of the chip, rows of at least 16
-        const long long target = 3 * 256 * 4;
+        // about twelve work items per resident wave, rows of at least 16
+        const long long target = 12LL * e->n_cu * 4 * e->march_blocks_per_cu;
         const long long per_chunk = (long long)L.R * ma.nstrip;
         long long nch = (target + per_chunk - 1) / per_chunk;
         if (nch < 1)
@@ -178,7 +180,11 @@ MarchArgs march_args(const vlbm_ensemble *e, const LevelArgs &L, unsigned *grid)
     ma.chunk = chunk;
     ma.nchunk = (L.ny + chunk - 1) / chunk;
     const long long waves = (long long)L.R * ma.nstrip * ma.nchunk;
-    ma.nblocks = (int)((waves + 3) / 4);
+    long long blocks = (waves + 3) / 4;
+    const long long resident = (long long)e->n_cu * e->march_blocks_per_cu;
+    if (blocks > resident)
+        blocks = resident;
+    ma.nblocks = (int)blocks;
     ma.per_xcd = (ma.nblocks + 7) / 8;
     *grid = (unsigned)(8 * ma.per_xcd);
     return ma;
@@ -320,6 +326,19 @@ vlbm_status vlbm_init_ensemble(const vlbm_params *p, const vlbm_level *levels, i
     if (he != hipSuccess) {
         vlbm_destroy(e);
         return fail(VLBM_ERR_HIP, "initialisation copy failed: %s", hipGetErrorString(he));
+    }
+    {
+        int dev = 0;
+        hipDeviceProp_t prop;
+        if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess &&
+            prop.multiProcessorCount > 0)
+            e->n_cu = prop.multiProcessorCount;
+        int occ = 0;
+        hipError_t oe = p->precision == VLBM_FP64
+                            ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, step_march_kernel<0>, 256, 0)
+                            : hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, step_march_kernel<1>, 256, 0);
+        if (oe == hipSuccess && occ > 0)
+            e->march_blocks_per_cu = occ;
     }
     const PhysArgs ph = phys_args(*p);
     for (const LevelArgs &L : e->levels) {

@@ -74,9 +74,10 @@ __device__ __forceinline__ void cell_bounds(const Phys &P, const double L[4], do
                                             double rho_c, double *rmin_out, double *rmax_out,
                                             double *rhoe_out)
 {
-    const double b1 = m1w_rho / P.w, b2 = m2e_rho / P.w, b3 = m3s_rho / P.w, b4 = m4n_rho / P.w;
-    double rmax = fmax(fmax(b1, b2), fmax(b3, b4));
-    double rmin = fmin(fmin(b1, b2), fmin(b3, b4));
+    // Division by w > 0 is monotone, so the largest (smallest) bar density
+    // max_k M_k/w equals (max_k M_k)/w bit for bit: two divisions, not four.
+    double rmax = fmax(fmax(m1w_rho, m2e_rho), fmax(m3s_rho, m4n_rho)) / P.w;
+    double rmin = fmin(fmin(m1w_rho, m2e_rho), fmin(m3s_rho, m4n_rho)) / P.w;
     if (P.alpha > 0.0) {
         rmax = fmax(rmax, rho_c);
         rmin = fmin(rmin, rho_c);
@@ -85,6 +86,20 @@ __device__ __forceinline__ void cell_bounds(const Phys &P, const double L[4], do
     *rmax_out = rmax + delta;
     *rmin_out = fmax(rmin - delta, 0.5 * rmin);
     *rhoe_out = L[3] - 0.5 * (L[1] * L[1] + L[2] * L[2]) / L[0];
+}
+
+// Maxwellian M_4 alone (the only one a node contributes to the low-order
+// state of the node below it), same operation order as maxwellians().
+__device__ __forceinline__ void maxwellian4(const Phys &P, const double u[4], double M4[4])
+{
+    const double rho = u[0], m1 = u[1], m2 = u[2], E = u[3];
+    const double v1 = m1 / rho;
+    const double v2 = m2 / rho;
+    const double p = (P.gamma - 1.0) * (E - 0.5 * rho * (v1 * v1 + v2 * v2));
+    const double g[4] = {m2, m2 * v1, m2 * v2 + p, (E + p) * v2};
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+        M4[v] = P.w * u[v] - P.h * g[v];
 }
 
 // Largest theta in [0,1] keeping L + theta*D inside [rmin, rmax] in density and
@@ -294,6 +309,7 @@ __device__ __forceinline__ StepCtl step_control(double t, double amax, double ka
 // planes as float (same index), padded to 256 B, then the var 3 planes as double.
 // ---------------------------------------------------------------------------
 struct StateFP64 {
+    typedef double elem;
     double *p;
     size_t plane; // ny * nx
     int R;
@@ -305,6 +321,19 @@ struct StateFP64 {
     __device__ __forceinline__ void st(int v, int s, int m, size_t node, double x) const { p[idx(v, s, m, node)] = x; }
     // value a store of x in variable v reads back as
     __device__ __forceinline__ double stored(int, double x) const { return x; }
+    // wave-uniform base of plane (v, s) of realization m; elements addressed by a
+    // 32-bit byte offset (node * element size)
+    __device__ __forceinline__ const char *plane_base(int v, int s, int m) const
+    {
+        return (const char *)(p + ((size_t)(v * 5 + s) * (size_t)R + (size_t)m) * plane);
+    }
+    __device__ __forceinline__ char *plane_w(int v, int s, int m) const { return (char *)plane_base(v, s, m); }
+    __device__ static __forceinline__ unsigned esize(int) { return 8u; }
+    __device__ static __forceinline__ double ldp(const char *base, int, unsigned off)
+    {
+        return *(const double *)(base + off);
+    }
+    __device__ static __forceinline__ void stp(char *base, int, unsigned off, double x) { *(double *)(base + off) = x; }
 };
 
 struct StateMixed {
@@ -326,6 +355,27 @@ struct StateMixed {
             pd[((size_t)s * (size_t)R + (size_t)m) * plane + node] = x;
     }
     __device__ __forceinline__ double stored(int v, double x) const { return v < 3 ? (double)(float)x : x; }
+    __device__ __forceinline__ const char *plane_base(int v, int s, int m) const
+    {
+        if (v < 3)
+            return (const char *)(pf + ((size_t)(v * 5 + s) * (size_t)R + (size_t)m) * plane);
+        return (const char *)(pd + ((size_t)s * (size_t)R + (size_t)m) * plane);
+    }
+    __device__ __forceinline__ char *plane_w(int v, int s, int m) const { return (char *)plane_base(v, s, m); }
+    __device__ static __forceinline__ unsigned esize(int v) { return v < 3 ? 4u : 8u; }
+    __device__ static __forceinline__ double ldp(const char *base, int v, unsigned off)
+    {
+        if (v < 3)
+            return (double)*(const float *)(base + off);
+        return *(const double *)(base + off);
+    }
+    __device__ static __forceinline__ void stp(char *base, int v, unsigned off, double x)
+    {
+        if (v < 3)
+            *(float *)(base + off) = (float)x;
+        else
+            *(double *)(base + off) = x;
+    }
 };
 
 // Launch arguments of one mesh level and of the physics (plain values).

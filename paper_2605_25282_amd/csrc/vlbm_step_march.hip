@@ -6,46 +6,73 @@
 // output columns, lanes 0, 1, 62, 63 are the halo the radius-2 stencil needs.
 // The wave marches up its rows.  Iteration k reads the macroscopic row k and
 // the population row k-1 (both prefetched one iteration ahead) and
-//   S1  computes the Maxwellians M(k)                      (eq:maxwellians12-34)
-//   S2  forms the low-order state and density bounds of row k-1, its
-//       non-equilibrium parts N(k-1) = M(k-1) - u_k(k-1) and the blending
-//       parameter of every x-face of row k-1
-//   S3  forms the blending parameter of the y-faces between rows k-2 and k-1
-//       and writes row k-2 (eq:vlbm1-5).
-// Every quantity of a node is computed once; x-neighbours are exchanged with
-// cross-lane shuffles, y-neighbours live in a three-row register ring.  Each
-// value of the state is read from HBM once (plus the 4-column and 4-row halos)
-// and written once: 320 B per FP64 node update.
+//   - forms the Maxwellians (eq:maxwellians12-34) and non-equilibrium parts
+//     N = M - u_k of row k-1, its low-order state, density bounds and the
+//     blending parameter of its east x-face,
+//   - forms the blending parameter of the y-face between rows k-2 and k-1,
+//   - finishes row k-2 (u_4 and u of eq:vlbm4-5) and
+//   - writes u_1..u_3 of row k-1 (eq:vlbm1-3), which no longer depend on
+//     anything unknown, keeping only the partial sums of eq:vlbm5.
+// Only four 4-vectors per node (partial sum, partial correction, N_3, M_3)
+// plus the low-order state travel to the next iteration.
+// x-neighbours are exchanged with DPP lane shifts.  Each value of the state is
+// read from HBM once (plus the 4-column and 4-row halos) and written once:
+// 320 B per FP64 node update.
 //
 // Every arithmetic expression has the operand order of the reference form in
 // vlbm_kernels.hip (and of the oracle), so the result is bitwise identical.
 //
 // Boundary layers (Dirichlet inlet column, zero-gradient copy columns and
-// rows) are produced by the wave that owns the copied interior node.  Blocks
-// are renumbered so that consecutive work lands on one XCD (shared L2 for the
-// halo re-reads).
+// rows) are produced by the wave that owns the copied interior node.
+//
+// Work items (realization, row chunk, strip) are ordered strip-fastest and
+// dealt round-robin to a grid sized to the resident capacity of the chip;
+// blocks are renumbered so that consecutive items land on one XCD (shared L2
+// for the halo re-reads of neighbouring strips and chunks).
 #include "vlbm_device.h"
 
 namespace vlbm {
 
 struct MarchArgs {
-    int nstrip;     // column strips per realization
-    int chunk;      // rows per work item
-    int nchunk;     // row chunks per realization
-    int nblocks;    // logical blocks (4 waves each)
-    int per_xcd;    // logical blocks per XCD slot
+    int nstrip;      // column strips per realization
+    int chunk;       // rows per work item
+    int nchunk;      // row chunks per realization
+    int nblocks;     // logical blocks (4 waves each); waves loop over the work items
+    int per_xcd;     // logical blocks per XCD slot
     int lane62_last; // 1: lane 62 of the last strip writes the copy column nx-1
 };
 
 static constexpr int STRIP = 60;
 
-__device__ __forceinline__ double from_left(double x) { return __shfl_up(x, 1, 64); }
-__device__ __forceinline__ double from_right(double x) { return __shfl_down(x, 1, 64); }
-__device__ __forceinline__ int from_left_i(int x) { return __shfl_up(x, 1, 64); }
-__device__ __forceinline__ int from_right_i(int x) { return __shfl_down(x, 1, 64); }
+// Minimum resident blocks per CU the register allocation is held to (1 leaves
+// the full 512-entry register file to one wave per SIMD).
+#ifndef VLBM_MARCH_MIN_BLOCKS
+#define VLBM_MARCH_MIN_BLOCKS 1
+#endif
+
+// Lane exchange along the strip: lane i receives the value of lane i-1
+// (from_left) or lane i+1 (from_right).  DPP wavefront shifts by one lane
+// (a VALU operand modifier, no LDS round trip); the end lanes keep their own
+// value, which only halo lanes ever read.
+__device__ __forceinline__ int dpp_left_i(int x) { return __builtin_amdgcn_update_dpp(x, x, 0x138, 0xf, 0xf, false); }
+__device__ __forceinline__ int dpp_right_i(int x) { return __builtin_amdgcn_update_dpp(x, x, 0x130, 0xf, 0xf, false); }
+__device__ __forceinline__ double from_left(double x)
+{
+    const long long b = __double_as_longlong(x);
+    const int lo = dpp_left_i((int)(b & 0xffffffffll)), hi = dpp_left_i((int)(b >> 32));
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+__device__ __forceinline__ double from_right(double x)
+{
+    const long long b = __double_as_longlong(x);
+    const int lo = dpp_right_i((int)(b & 0xffffffffll)), hi = dpp_right_i((int)(b >> 32));
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+__device__ __forceinline__ int from_left_i(int x) { return dpp_left_i(x); }
+__device__ __forceinline__ int from_right_i(int x) { return dpp_right_i(x); }
 
 template <int PREC>
-__global__ void __launch_bounds__(256, 1)
+__global__ void __launch_bounds__(256, VLBM_MARCH_MIN_BLOCKS)
 step_march_kernel(PhysArgs ph, LevelArgs L, Ctl ctl, int phase, double t_final, MarchArgs ma)
 {
     const int b = blockIdx.x;
@@ -53,12 +80,15 @@ step_march_kernel(PhysArgs ph, LevelArgs L, Ctl ctl, int phase, double t_final, 
     if (lb >= ma.nblocks)
         return;
     const int lane = threadIdx.x & 63;
-    const long long gw = (long long)lb * 4 + (threadIdx.x >> 6);
     const long long per_real = (long long)ma.nstrip * ma.nchunk;
-    if (gw >= per_real * L.R)
-        return;
-    const int m = (int)(gw / per_real);
-    const int rem = (int)(gw % per_real);
+    const long long n_items = per_real * L.R;
+    const long long grid_waves = (long long)ma.nblocks * 4;
+    // the wave index is uniform across the wave: keep it (and everything derived
+    // from it: work item, realization, plane bases, time control) in scalar registers
+    const int wid = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    for (long long item = (long long)lb * 4 + wid; item < n_items; item += grid_waves) {
+    const int m = (int)(item / per_real);
+    const int rem = (int)(item % per_real);
     const int chunk = rem / ma.nstrip, strip = rem % ma.nstrip;
 
     // ---- time-step control (identical in every wave of the realization) ----
@@ -77,7 +107,7 @@ step_march_kernel(PhysArgs ph, LevelArgs L, Ctl ctl, int phase, double t_final, 
             ctl.amax[r1 * nr + cm] = ctl.amax[r0 * nr + cm];
             ctl.amax[r2 * nr + cm] = 0ull;
         }
-        return;
+        continue;
     }
     if (lead) {
         ctl.t[r1 * nr + cm] = sc.t_new;
@@ -89,8 +119,23 @@ step_march_kernel(PhysArgs ph, LevelArgs L, Ctl ctl, int phase, double t_final, 
     const int nx = L.nx, ny = L.ny, bc = ph.bc, lim = ph.limiter;
     const bool periodic = bc == BC_PERIODIC;
     const size_t plane = (size_t)nx * ny;
-    const auto Sin = StateOf<PREC>::make(L.buf[s & 1], plane, L.R);
-    const auto Sout = StateOf<PREC>::make(L.buf[(s + 1) & 1], plane, L.R);
+    typedef typename StateOf<PREC>::type St;
+    const St Sin = StateOf<PREC>::make(L.buf[s & 1], plane, L.R);
+    const St Sout = StateOf<PREC>::make(L.buf[(s + 1) & 1], plane, L.R);
+    // wave-uniform plane bases of the input buffer; the output buffer has the
+    // same layout, so its planes sit one uniform byte distance further on
+    const char *inU[4], *inP[4][4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        inU[v] = Sin.plane_base(v, 0, m);
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            inP[q][v] = Sin.plane_base(v, 1 + q, m);
+    }
+    const long long out_delta = (const char *)L.buf[(s + 1) & 1] - (const char *)L.buf[s & 1];
+    auto out_plane = [&](int sl, int v) -> char * {
+        return (char *)(sl == 0 ? inU[v] : inP[sl - 1][v]) + out_delta;
+    };
 
     // ---- geometry of this lane ----
     const int c = strip * STRIP - 2 + lane; // column
@@ -117,93 +162,116 @@ step_march_kernel(PhysArgs ph, LevelArgs L, Ctl ctl, int phase, double t_final, 
             return true;
         return kind_col_interior && j >= 1 && j <= ny - 2;
     };
-
-    // ---- register ring ----
-    double U0[4], U1[4], U2[4];       // macroscopic rows k, k-1, k-2
-    double MA[4][4], MB[4][4];        // Maxwellians of rows k, k-1
-    double MC[3][4];                  // M_1..M_3 of row k-2
-    double NB[4][4], NC[4][4];        // non-equilibrium parts of rows k-1, k-2
-    double LB[4], LC[4];              // low-order states of rows k-1, k-2
-    double bB[3], bC[3];              // (rho_min', rho_max', rho e_L) of rows k-1, k-2
-    double txB = 0.0, txC = 0.0;      // theta of the east x-face, rows k-1, k-2
-    double tyD = 0.0;                 // theta of the y-face between rows k-3 and k-2
-    double o3D[4];                    // streamed population 3 leaving row k-3
-    double Un[4], Pn[4][4];           // prefetch: U(k+1), populations of row k
+    auto off_of = [&](int j, int col, int v) -> unsigned {
+        return (unsigned)((size_t)j * nx + col) * St::esize(v);
+    };
     double wmax = 0.0;
     int bad = 0;
+    auto store_slot = [&](int sl, int j, const double x[4]) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+            St::stp(out_plane(sl, v), v, off_of(j, c, v), x[v]);
+    };
+    auto account = [&](const double u[4]) {
+        double us[4];
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+            us[v] = Sout.stored(v, u[v]);
+        int b2 = 0;
+        wmax = fmax(wmax, wave_speed(ph.gamma, us, &b2));
+        const bool fin = isfinite(us[0]) && isfinite(us[1]) && isfinite(us[2]) && isfinite(us[3]);
+        bad |= !fin ? STATUS_NONFINITE : (b2 ? STATUS_NONPOSITIVE : 0);
+    };
+    auto shuffle_copy = [&](double x[4]) {
+        if (wave_copy) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const double fl = from_left(x[v]);
+                const double fr = from_right(x[v]);
+                if (copy_from_left)
+                    x[v] = fl;
+                else if (copy_from_right)
+                    x[v] = fr;
+            }
+        }
+    };
+    // a scheme row (not the inlet column) written at row j, duplicated into the
+    // zero-gradient rows 0 / ny-1 when j is the adjacent interior row
+    auto row_stored = [&](int j) { return out_lane && !inlet_col && j >= y0 && j < y1 && (periodic || (j != 0 && j != ny - 1)); };
+    // (a level with ny = 3 duplicates its single interior row into both)
+    auto dup_lo = [&](int j) { return !periodic && j == 1; };
+    auto dup_hi = [&](int j) { return !periodic && j == ny - 2; };
+
+    // ---- register ring ----
+    // Row k-2, finished in iteration k: (u1+u2)+u3, the correction without its
+    // north-face term, N_3 and M_3, the low-order state and its bounds.
+    double U0[4], U1[4];
+    double pC[4], cC[4], N3C[4], M3C[4], LC[4], bC[3];
+    double Un[4], Pn[4][4]; // loads in flight: U(k+1), populations of row k
 
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
-        U1[v] = U2[v] = LB[v] = LC[v] = o3D[v] = 0.0;
+        U1[v] = (v == 0 || v == 3) ? 1.0 : 0.0; // placeholder row before the first load
+        pC[v] = cC[v] = N3C[v] = M3C[v] = LC[v] = 0.0;
 #pragma unroll
         for (int q = 0; q < 4; ++q)
-            MB[q][v] = NB[q][v] = NC[q][v] = 0.0;
-#pragma unroll
-        for (int q = 0; q < 3; ++q)
-            MC[q][v] = 0.0;
+            Pn[q][v] = 0.0;
     }
-    bB[0] = bB[1] = bB[2] = bC[0] = bC[1] = bC[2] = 0.0;
+    bC[0] = bC[1] = bC[2] = 0.0;
 
     const int k_first = y0 - 2, k_last = y1 + 1;
-    {
-        const size_t n0 = (size_t)row_of(k_first) * nx + cx;
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+        Un[v] = St::ldp(inU[v], v, off_of(row_of(k_first), cx, v));
+
+    for (int k = k_first; k <= k_last; ++k) {
 #pragma unroll
         for (int v = 0; v < 4; ++v)
-            Un[v] = Sin.ld(v, 0, m, n0);
+            U0[v] = Un[v];
+        // Row k-1: Maxwellians and non-equilibrium parts (its populations arrived).
+        double MB[4][4], NB[4][4];
+        maxwellians(P, U1, MB);
 #pragma unroll
         for (int q = 0; q < 4; ++q)
 #pragma unroll
             for (int v = 0; v < 4; ++v)
-                Pn[q][v] = 0.0;
-    }
-
-    for (int k = k_first; k <= k_last; ++k) {
-        double Pc[4][4];
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            U0[v] = Un[v];
-#pragma unroll
-            for (int q = 0; q < 4; ++q)
-                Pc[q][v] = Pn[q][v];
-        }
-        // prefetch the next rows
+                NB[q][v] = MB[q][v] - Pn[q][v];
+        // Issue the next loads: macroscopic row k+1 and population row k.
         if (k < k_last) {
-            const size_t nu = (size_t)row_of(k + 1) * nx + cx;
+            const int jr = row_of(k + 1);
 #pragma unroll
             for (int v = 0; v < 4; ++v)
-                Un[v] = Sin.ld(v, 0, m, nu);
+                Un[v] = St::ldp(inU[v], v, off_of(jr, cx, v));
         }
-        if (k >= y0 - 1 && k <= y1) { // population row k is used (as row k-1) next iteration
-            const size_t np = (size_t)row_of(k) * nx + cx;
+        if (k >= y0 - 1 && k <= y1) { // population row k is row k-1 of the next iteration
+            const int jr = row_of(k);
 #pragma unroll
             for (int q = 0; q < 4; ++q)
 #pragma unroll
                 for (int v = 0; v < 4; ++v)
-                    Pn[q][v] = Sin.ld(v, 1 + q, m, np);
+                    Pn[q][v] = St::ldp(inP[q][v], v, off_of(jr, cx, v));
         }
 
-        // S1: Maxwellians of row k
-        maxwellians(P, U0, MA);
-
-        // S2: row k-1
+        // Low-order state and bounds of row k-1.
         const int jB = k - 1;
-        double M1w[4], M2e[4];
+        double LB[4], bB[3];
+        {
+            double M4n[4];
+            maxwellian4(P, U0, M4n); // row k
+            double M1w[4], M2e[4];
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            M1w[v] = from_left(MB[0][v]);
-            M2e[v] = from_right(MB[1][v]);
-        }
-#pragma unroll
-        for (int v = 0; v < 4; ++v)
-            LB[v] = P.alpha * U1[v] + M1w[v] + M2e[v] + MC[2][v] + MA[3][v];
-        cell_bounds(P, LB, M1w[0], M2e[0], MC[2][0], MA[3][0], U1[0], &bB[0], &bB[1], &bB[2]);
-#pragma unroll
-        for (int q = 0; q < 4; ++q)
+            for (int v = 0; v < 4; ++v) {
+                M1w[v] = from_left(MB[0][v]);
+                M2e[v] = from_right(MB[1][v]);
+            }
 #pragma unroll
             for (int v = 0; v < 4; ++v)
-                NB[q][v] = MB[q][v] - Pc[q][v];
+                LB[v] = P.alpha * U1[v] + M1w[v] + M2e[v] + M3C[v] + M4n[v];
+            cell_bounds(P, LB, M1w[0], M2e[0], M3C[0], M4n[0], U1[0], &bB[0], &bB[1], &bB[2]);
+        }
+        // theta of the east x-face of row k-1
+        double txB = 0.0;
         {
-            // x-face between this column and the next, row k-1
             double Lr[4], br[3], N2r[4];
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
@@ -215,12 +283,11 @@ step_march_kernel(PhysArgs ph, LevelArgs L, Ctl ctl, int phase, double t_final, 
                 br[q] = from_right(bB[q]);
             const bool in1 = interior(jB);
             const int in2 = from_right_i((int)in1);
-            double th = 0.0;
             if (in1 || in2) {
                 if (lim == LIM_ZERO) {
-                    th = 0.0;
+                    txB = 0.0;
                 } else if (lim == LIM_ONE) {
-                    th = 1.0;
+                    txB = 1.0;
                 } else {
                     double Dup[4], Ddn[4];
 #pragma unroll
@@ -229,21 +296,19 @@ step_march_kernel(PhysArgs ph, LevelArgs L, Ctl ctl, int phase, double t_final, 
                         Dup[v] = -4.0 * A;
                         Ddn[v] = 4.0 * A;
                     }
-                    th = 1.0;
+                    txB = 1.0;
                     if (in1)
-                        th = fmin(th, side_theta(P, LB, bB[0], bB[1], bB[2], Dup));
+                        txB = fmin(txB, side_theta(P, LB, bB[0], bB[1], bB[2], Dup));
                     if (in2)
-                        th = fmin(th, side_theta(P, Lr, br[0], br[1], br[2], Ddn));
+                        txB = fmin(txB, side_theta(P, Lr, br[0], br[1], br[2], Ddn));
                 }
             }
-            txB = th;
         }
-
-        // S3: row r = k-2
+        // theta of the y-face between rows k-2 and k-1
         const int r = k - 2;
         double tyC = 0.0;
         {
-            const bool in1 = interior(r), in2 = interior(r + 1);
+            const bool in1 = interior(r), in2 = interior(jB);
             if (in1 || in2) {
                 if (lim == LIM_ZERO) {
                     tyC = 0.0;
@@ -253,7 +318,7 @@ step_march_kernel(PhysArgs ph, LevelArgs L, Ctl ctl, int phase, double t_final, 
                     double Dup[4], Ddn[4];
 #pragma unroll
                     for (int v = 0; v < 4; ++v) {
-                        const double A = NC[2][v] - NB[3][v];
+                        const double A = N3C[v] - NB[3][v];
                         Dup[v] = -4.0 * A;
                         Ddn[v] = 4.0 * A;
                     }
@@ -265,111 +330,89 @@ step_march_kernel(PhysArgs ph, LevelArgs L, Ctl ctl, int phase, double t_final, 
                 }
             }
         }
-        const double txw = from_left(txC);
-        double R[5][4], o3C[4];
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const double out1 = MC[0][v] + txC * NC[0][v];
-            const double out2 = MC[1][v] + txw * NC[1][v];
-            o3C[v] = MC[2][v] + tyC * NC[2][v];
-            const double u4 = MB[3][v] + tyC * NB[3][v];
-            const double corr = P.alpha * U2[v] - txw * NC[1][v] - txC * NC[0][v] - tyD * NC[3][v] - tyC * NC[2][v];
-            const double u1 = from_left(out1);
-            const double u2 = from_right(out2);
-            const double u3 = o3D[v];
-            R[1][v] = u1;
-            R[2][v] = u2;
-            R[3][v] = u3;
-            R[4][v] = u4;
-            R[0][v] = (u1 + u2 + u3 + u4) + corr;
-        }
-        // copy columns take the result of the adjacent (interior) column
-        if (wave_copy) {
-#pragma unroll
-            for (int sl = 0; sl < 5; ++sl)
-#pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                    const double fl = from_left(R[sl][v]);
-                    const double fr = from_right(R[sl][v]);
-                    if (copy_from_left)
-                        R[sl][v] = fl;
-                    else if (copy_from_right)
-                        R[sl][v] = fr;
-                }
-        }
-        // Dirichlet inlet column (eq:inletBC): u kept, populations at equilibrium for a_n
-        if (inlet_wave) {
-            double Mi[4][4];
-            maxwellians(P, U2, Mi);
+
+        // Finish row k-2 (eq:vlbm4 and eq:vlbm5): u_4 and the macroscopic state.
+        {
+            double u4[4], u0[4];
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                R[0][v] = inlet_col ? U2[v] : R[0][v];
-#pragma unroll
-                for (int q = 0; q < 4; ++q)
-                    R[1 + q][v] = inlet_col ? Mi[q][v] : R[1 + q][v];
+                u4[v] = MB[3][v] + tyC * NB[3][v];
+                u0[v] = (pC[v] + u4[v]) + (cC[v] - tyC * N3C[v]);
+            }
+            shuffle_copy(u4);
+            shuffle_copy(u0);
+            if (row_stored(r)) {
+                store_slot(0, r, u0);
+                store_slot(4, r, u4);
+                account(u0);
+                if (dup_lo(r)) {
+                    store_slot(0, 0, u0);
+                    store_slot(4, 0, u4);
+                }
+                if (dup_hi(r)) {
+                    store_slot(0, ny - 1, u0);
+                    store_slot(4, ny - 1, u4);
+                }
             }
         }
-        // ---- store row r ----
-        if (out_lane && r >= y0 && r < y1) {
-            const bool copy_row = !periodic && (r == 0 || r == ny - 1);
-            if (inlet_col || !copy_row) {
-                const size_t n = (size_t)r * nx + c;
+        // Row k-1: populations u_1..u_3 (eq:vlbm1-3) are final; keep the partial
+        // sums of eq:vlbm5 for the next iteration.
+        const double txw = from_left(txB);
+        double pB[4], cB[4];
+        {
+            double u1[4], u2[4], u3[4];
 #pragma unroll
-                for (int sl = 0; sl < 5; ++sl)
-#pragma unroll
-                    for (int v = 0; v < 4; ++v)
-                        Sout.st(v, sl, m, n, R[sl][v]);
-                double us[4];
-#pragma unroll
-                for (int v = 0; v < 4; ++v)
-                    us[v] = Sout.stored(v, R[0][v]);
-                int b2 = 0;
-                wmax = fmax(wmax, wave_speed(ph.gamma, us, &b2));
-                const bool fin = isfinite(us[0]) && isfinite(us[1]) && isfinite(us[2]) && isfinite(us[3]);
-                bad |= !fin ? STATUS_NONFINITE : (b2 ? STATUS_NONPOSITIVE : 0);
-                // zero-gradient rows copy the adjacent interior row (not the inlet corners)
-                if (!periodic && !inlet_col && (r == 1 || r == ny - 2)) {
-                    if (r == 1) {
-                        const size_t n2 = (size_t)c;
-#pragma unroll
-                        for (int sl = 0; sl < 5; ++sl)
-#pragma unroll
-                            for (int v = 0; v < 4; ++v)
-                                Sout.st(v, sl, m, n2, R[sl][v]);
-                    }
-                    if (r == ny - 2) {
-                        const size_t n2 = (size_t)(ny - 1) * nx + c;
-#pragma unroll
-                        for (int sl = 0; sl < 5; ++sl)
-#pragma unroll
-                            for (int v = 0; v < 4; ++v)
-                                Sout.st(v, sl, m, n2, R[sl][v]);
-                    }
+            for (int v = 0; v < 4; ++v) {
+                const double out1 = MB[0][v] + txB * NB[0][v];
+                const double out2 = MB[1][v] + txw * NB[1][v];
+                u1[v] = from_left(out1);
+                u2[v] = from_right(out2);
+                u3[v] = M3C[v] + tyC * N3C[v];
+                pB[v] = (u1[v] + u2[v]) + u3[v];
+                cB[v] = ((P.alpha * U1[v] - txw * NB[1][v]) - txB * NB[0][v]) - tyC * NB[3][v];
+            }
+            shuffle_copy(u1);
+            shuffle_copy(u2);
+            shuffle_copy(u3);
+            if (row_stored(jB)) {
+                store_slot(1, jB, u1);
+                store_slot(2, jB, u2);
+                store_slot(3, jB, u3);
+                if (dup_lo(jB)) {
+                    store_slot(1, 0, u1);
+                    store_slot(2, 0, u2);
+                    store_slot(3, 0, u3);
                 }
+                if (dup_hi(jB)) {
+                    store_slot(1, ny - 1, u1);
+                    store_slot(2, ny - 1, u2);
+                    store_slot(3, ny - 1, u3);
+                }
+            }
+            // Dirichlet inlet column (eq:inletBC): u kept, populations at
+            // equilibrium for this step's kinetic speed.
+            if (inlet_wave && out_lane && inlet_col && jB >= y0 && jB < y1) {
+                store_slot(0, jB, U1);
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    store_slot(1 + q, jB, MB[q]);
+                account(U1);
             }
         }
 
         // ---- rotate the ring ----
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-            U2[v] = U1[v];
             U1[v] = U0[v];
-#pragma unroll
-            for (int q = 0; q < 3; ++q)
-                MC[q][v] = MB[q][v];
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                MB[q][v] = MA[q][v];
-                NC[q][v] = NB[q][v];
-            }
+            pC[v] = pB[v];
+            cC[v] = cB[v];
+            N3C[v] = NB[2][v];
+            M3C[v] = MB[2][v];
             LC[v] = LB[v];
-            o3D[v] = o3C[v];
         }
         bC[0] = bB[0];
         bC[1] = bB[1];
         bC[2] = bB[2];
-        txC = txB;
-        tyD = tyC;
     }
 
     // ---- wave-speed maximum (next a_n) and latched status ----
@@ -383,6 +426,7 @@ step_march_kernel(PhysArgs ph, LevelArgs L, Ctl ctl, int phase, double t_final, 
         if (bad)
             atomicOr(&ctl.status[cm], bad & STATUS_NONFINITE ? STATUS_NONFINITE : STATUS_NONPOSITIVE);
     }
+    } // work items
 }
 
 template __global__ void step_march_kernel<0>(PhysArgs, LevelArgs, Ctl, int, double, MarchArgs);
