@@ -227,6 +227,22 @@ vlbm_status vlbm_w1(const double *sorted_a, const double *sorted_b, int64_t n_ce
  */
 vlbm_status vlbm_tune(vlbm_ensemble *e, int32_t kernel, int32_t chunk_rows);
 
+/*
+ * Autotune the marching kernel's row chunk for every level on live steps:
+ * candidate chunk heights are ranked by a work model (rounds of resident
+ * wavefronts times rows per item including the 4-row prologue), the best few
+ * are each timed over steps_per_candidate real steps of this ensemble (HIP
+ * events per level on the ensemble's stream), and the fastest is kept.  The
+ * steps taken are ordinary steps toward t_final (every configuration is
+ * bit-identical), so tuning wastes no work.  Results are cached per (nx, ny,
+ * n_real, precision, bc, limiter) for the lifetime of the process and applied
+ * automatically to ensembles created later with the same shape.
+ *   chunks_out: HOST array [n_levels] receiving the chosen chunk heights, or NULL.
+ * Synchronizes the stream.
+ */
+vlbm_status vlbm_autotune(vlbm_ensemble *e, double t_final, int32_t steps_per_candidate,
+                          int32_t *chunks_out);
+
 /* Release the handle and its control arrays (synchronizes its stream). */
 vlbm_status vlbm_destroy(vlbm_ensemble *e);
 

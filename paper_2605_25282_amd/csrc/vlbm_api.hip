@@ -9,8 +9,12 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <algorithm>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "../../include/vlbm.h"
@@ -145,36 +149,59 @@ struct vlbm_ensemble {
     int chunk_rows = 0;     // 0 = automatic
     int n_cu = 256;         // compute units of the device
     int march_blocks_per_cu = 1;
+    std::vector<int> level_chunk; // per-level chunk override (0 = from chunk_rows / model)
 };
+
+namespace {
+// Process-wide cache of tuned chunk heights.
+typedef std::tuple<int, int, int, int, int, int> TuneKey; // nx, ny, R, precision, bc, limiter
+std::map<TuneKey, int> g_tune_cache;
+std::mutex g_tune_mu;
+
+TuneKey tune_key(const vlbm_ensemble *e, const LevelArgs &L)
+{
+    return TuneKey(L.nx, L.ny, L.R, e->p.precision, e->p.bc, e->p.limiter);
+}
+} // namespace
 
 namespace {
 
 int phase_of(const vlbm_ensemble *e) { return (int)(e->n_launch % 3); }
 
 // Work decomposition of the marching kernel for one level.
-MarchArgs march_args(const vlbm_ensemble *e, const LevelArgs &L, unsigned *grid)
+int strips_of(const vlbm_ensemble *e, const LevelArgs &L, int *lane62)
 {
-    MarchArgs ma{};
     const bool periodic = e->p.bc == VLBM_BC_PERIODIC;
     if (!periodic && (L.nx - 1) % 60 == 0) {
-        ma.nstrip = (L.nx - 1) / 60;
-        ma.lane62_last = 1;
-    } else {
-        ma.nstrip = (L.nx + 59) / 60;
-        ma.lane62_last = 0;
+        *lane62 = 1;
+        return (L.nx - 1) / 60;
     }
-    int chunk = e->chunk_rows;
-    if (chunk <= 0) {
-        // about twelve work items per resident wave, rows of at least 16
-        const long long target = 12LL * e->n_cu * 4 * e->march_blocks_per_cu;
-        const long long per_chunk = (long long)L.R * ma.nstrip;
-        long long nch = (target + per_chunk - 1) / per_chunk;
-        if (nch < 1)
-            nch = 1;
-        chunk = (int)((L.ny + nch - 1) / nch);
-        if (chunk < 16)
-            chunk = 16;
-    }
+    *lane62 = 0;
+    return (L.nx + 59) / 60;
+}
+
+// Default chunk height: about twelve work items per resident wave, rows >= 16.
+int model_chunk(const vlbm_ensemble *e, const LevelArgs &L, int nstrip)
+{
+    const long long target = 12LL * e->n_cu * 4 * e->march_blocks_per_cu;
+    const long long per_chunk = (long long)L.R * nstrip;
+    long long nch = (target + per_chunk - 1) / per_chunk;
+    if (nch < 1)
+        nch = 1;
+    int chunk = (int)((L.ny + nch - 1) / nch);
+    return chunk < 16 ? 16 : chunk;
+}
+
+MarchArgs march_args(const vlbm_ensemble *e, int level, unsigned *grid)
+{
+    const LevelArgs &L = e->levels[level];
+    MarchArgs ma{};
+    ma.nstrip = strips_of(e, L, &ma.lane62_last);
+    int chunk = e->level_chunk.empty() ? 0 : e->level_chunk[level];
+    if (chunk <= 0)
+        chunk = e->chunk_rows;
+    if (chunk <= 0)
+        chunk = model_chunk(e, L, ma.nstrip);
     if (chunk > L.ny)
         chunk = L.ny;
     ma.chunk = chunk;
@@ -190,8 +217,9 @@ MarchArgs march_args(const vlbm_ensemble *e, const LevelArgs &L, unsigned *grid)
     return ma;
 }
 
-vlbm_status launch_step(vlbm_ensemble *e, const PhysArgs &ph, const LevelArgs &L, int phase, double t_final)
+vlbm_status launch_step(vlbm_ensemble *e, const PhysArgs &ph, int level, int phase, double t_final)
 {
+    const LevelArgs &L = e->levels[level];
     if (e->kernel == VLBM_KERNEL_REFERENCE) {
         if (e->p.precision == VLBM_FP64)
             step_ref_kernel<0><<<node_grid(L), 256, 0, e->stream>>>(ph, L, e->ctl, phase, t_final);
@@ -199,7 +227,7 @@ vlbm_status launch_step(vlbm_ensemble *e, const PhysArgs &ph, const LevelArgs &L
             step_ref_kernel<1><<<node_grid(L), 256, 0, e->stream>>>(ph, L, e->ctl, phase, t_final);
     } else {
         unsigned grid = 0;
-        const MarchArgs ma = march_args(e, L, &grid);
+        const MarchArgs ma = march_args(e, level, &grid);
         if (e->p.precision == VLBM_FP64)
             step_march_kernel<0><<<grid, 256, 0, e->stream>>>(ph, L, e->ctl, phase, t_final, ma);
         else
@@ -355,6 +383,16 @@ vlbm_status vlbm_init_ensemble(const vlbm_params *p, const vlbm_level *levels, i
             return fail(VLBM_ERR_HIP, "init launch failed: %s", hipGetErrorString(le));
         }
     }
+    // Chunk heights tuned earlier in this process for the same shapes.
+    e->level_chunk.assign(e->levels.size(), 0);
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        for (size_t l = 0; l < e->levels.size(); ++l) {
+            auto it = g_tune_cache.find(tune_key(e, e->levels[l]));
+            if (it != g_tune_cache.end())
+                e->level_chunk[l] = it->second;
+        }
+    }
     // The host coefficient array may be released once this call returns.
     he = hipStreamSynchronize(e->stream);
     if (he != hipSuccess) {
@@ -424,8 +462,8 @@ vlbm_status vlbm_step(vlbm_ensemble *e, double t_final, int32_t n_steps, int32_t
     const PhysArgs ph = phys_args(e->p);
     for (int s = 0; s < n_steps; ++s) {
         const int phase = phase_of(e);
-        for (const LevelArgs &L : e->levels) {
-            vlbm_status rc = launch_step(e, ph, L, phase, t_final);
+        for (int l = 0; l < (int)e->levels.size(); ++l) {
+            vlbm_status rc = launch_step(e, ph, l, phase, t_final);
             if (rc != VLBM_OK)
                 return rc;
         }
@@ -603,6 +641,118 @@ vlbm_status vlbm_tune(vlbm_ensemble *e, int32_t kernel, int32_t chunk_rows)
         return fail(VLBM_ERR_ARG, "chunk_rows must be 0 or lie in [4, 65536] (got %d)", chunk_rows);
     e->kernel = kernel;
     e->chunk_rows = chunk_rows;
+    std::fill(e->level_chunk.begin(), e->level_chunk.end(), 0);
+    return VLBM_OK;
+}
+
+vlbm_status vlbm_autotune(vlbm_ensemble *e, double t_final, int32_t steps_per_candidate, int32_t *chunks_out)
+{
+    if (!e)
+        return fail(VLBM_ERR_ARG, "ensemble is NULL");
+    if (!std::isfinite(t_final))
+        return fail(VLBM_ERR_ARG, "t_final must be finite");
+    if (steps_per_candidate < 1 || steps_per_candidate > 1000)
+        return fail(VLBM_ERR_ARG, "steps_per_candidate must lie in [1, 1000]");
+    const int nlev = (int)e->levels.size();
+    if (e->kernel != VLBM_KERNEL_MARCH) {
+        if (chunks_out)
+            for (int l = 0; l < nlev; ++l)
+                chunks_out[l] = 0;
+        return VLBM_OK;
+    }
+    // Candidates per level, ranked by the work model.
+    const int max_cand = 6;
+    std::vector<std::vector<int>> cand(nlev);
+    const long long waves = (long long)e->n_cu * 4 * e->march_blocks_per_cu;
+    for (int l = 0; l < nlev; ++l) {
+        const LevelArgs &L = e->levels[l];
+        int lane62 = 0;
+        const int nstrip = strips_of(e, L, &lane62);
+        std::vector<std::pair<double, int>> ranked;
+        std::vector<int> seen;
+        for (int nch = 1; nch <= std::min(L.ny, 256); ++nch) {
+            int chunk = (L.ny + nch - 1) / nch;
+            if (chunk < 4)
+                chunk = 4;
+            if (std::find(seen.begin(), seen.end(), chunk) != seen.end())
+                continue;
+            seen.push_back(chunk);
+            const long long items = (long long)L.R * nstrip * ((L.ny + chunk - 1) / chunk);
+            const long long rounds = (items + waves - 1) / waves;
+            ranked.push_back({(double)rounds * (chunk + 4), chunk});
+        }
+        std::sort(ranked.begin(), ranked.end());
+        for (int i = 0; i < (int)ranked.size() && i < max_cand; ++i)
+            cand[l].push_back(ranked[i].second);
+        const int dflt = model_chunk(e, L, nstrip);
+        if (std::find(cand[l].begin(), cand[l].end(), dflt) == cand[l].end())
+            cand[l].push_back(dflt);
+    }
+    size_t ncand = 0;
+    for (auto &c : cand)
+        ncand = std::max(ncand, c.size());
+    std::vector<hipEvent_t> ev(nlev + 1);
+    for (auto &x : ev)
+        HIP_TRY(hipEventCreate(&x));
+    std::vector<std::vector<double>> ms(nlev, std::vector<double>(ncand, 0.0));
+    const PhysArgs ph = phys_args(e->p);
+    vlbm_status rc = VLBM_OK;
+    bool all_done = false;
+    for (size_t ci = 0; ci < ncand && rc == VLBM_OK && !all_done; ++ci) {
+        for (int l = 0; l < nlev; ++l)
+            e->level_chunk[l] = cand[l][std::min(ci, cand[l].size() - 1)];
+        for (int s = 0; s < steps_per_candidate && rc == VLBM_OK; ++s) {
+            const int phase = phase_of(e);
+            for (int l = 0; l < nlev && rc == VLBM_OK; ++l) {
+                if (hipEventRecord(ev[l], e->stream) != hipSuccess)
+                    rc = fail(VLBM_ERR_HIP, "hipEventRecord failed");
+                else
+                    rc = launch_step(e, ph, l, phase, t_final);
+            }
+            if (rc != VLBM_OK)
+                break;
+            e->n_launch++;
+            if (hipEventRecord(ev[nlev], e->stream) != hipSuccess || hipEventSynchronize(ev[nlev]) != hipSuccess) {
+                rc = fail(VLBM_ERR_HIP, "event synchronisation failed");
+                break;
+            }
+            for (int l = 0; l < nlev; ++l) {
+                float t = 0.f;
+                (void)hipEventElapsedTime(&t, ev[l], ev[l + 1]);
+                ms[l][ci] += t;
+            }
+        }
+        // stop early if the ensemble has finished (timings would be meaningless)
+        std::vector<double> t, a;
+        std::vector<long long> st;
+        std::vector<int> status;
+        if (rc == VLBM_OK && read_ctl(e, t, st, a, status) == VLBM_OK) {
+            all_done = true;
+            for (double x : t)
+                if (x < t_final)
+                    all_done = false;
+            if (all_done && ci == 0)
+                ms.assign(nlev, std::vector<double>(ncand, 0.0));
+        }
+    }
+    for (auto &x : ev)
+        (void)hipEventDestroy(x);
+    if (rc != VLBM_OK)
+        return rc;
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    for (int l = 0; l < nlev; ++l) {
+        int best = cand[l][0];
+        double best_ms = 1e300;
+        for (size_t ci = 0; ci < cand[l].size(); ++ci)
+            if (ms[l][ci] > 0.0 && ms[l][ci] < best_ms) {
+                best_ms = ms[l][ci];
+                best = cand[l][ci];
+            }
+        e->level_chunk[l] = best;
+        g_tune_cache[tune_key(e, e->levels[l])] = best;
+        if (chunks_out)
+            chunks_out[l] = best;
+    }
     return VLBM_OK;
 }
 

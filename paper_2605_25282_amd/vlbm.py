@@ -96,6 +96,7 @@ def lib():
             "vlbm_sort_samples": ([_VP, i64, i32, _VP], i32),
             "vlbm_w1": ([_VP, _VP, i64, i32, _VP, _VP, _VP], i32),
             "vlbm_tune": ([_VP, i32, i32], i32),
+            "vlbm_autotune": ([_VP, dbl, i32, ctypes.POINTER(i32)], i32),
             "vlbm_destroy": ([_VP], i32),
         }
         for name, (args, res) in sig.items():
@@ -202,6 +203,12 @@ def vlbm_tune(h, kernel: str | int = "march", chunk_rows: int = 0) -> None:
     _check(lib().vlbm_tune(h, k, chunk_rows))
 
 
+def vlbm_autotune(h, t_final: float, steps_per_candidate: int, n_levels: int) -> list[int]:
+    out = (ctypes.c_int32 * n_levels)()
+    _check(lib().vlbm_autotune(h, t_final, steps_per_candidate, out))
+    return list(out)
+
+
 def vlbm_destroy(h) -> None:
     _check(lib().vlbm_destroy(h))
 
@@ -240,6 +247,9 @@ class Ensemble:
 
     def tune(self, kernel: str | int = "march", chunk_rows: int = 0) -> None:
         vlbm_tune(self.h, kernel, chunk_rows)
+
+    def autotune(self, t_final: float, steps_per_candidate: int = 4) -> list[int]:
+        return vlbm_autotune(self.h, t_final, steps_per_candidate, len(self.shapes))
 
     def step(self, t_final: float, n_steps: int, want_done: bool = True):
         return vlbm_step(self.h, t_final, n_steps, want_done)

@@ -334,3 +334,26 @@ def test_march_kernel_equals_reference_jet640():
         del st
     assert np.array_equal(res["reference"][0], res["march"][0])
     assert np.array_equal(res["reference"][1], res["march"][1])
+
+
+def test_autotune_is_result_neutral_and_cached():
+    """Tuning runs live steps with several decompositions; the ensemble must end
+    bit-identical to an untuned one, and the choice must be reused by a new ensemble."""
+    w = inputs.WORKLOADS["jet128"]
+    R = 8
+    coefs = inputs.kl_coefficients(inputs.DEFAULT_SEED, 0, R)
+    a = vlbm.Ensemble(vlbm.Params.jet(), [(w.nx, w.ny, w.dx, w.y_min)], coefs, R)
+    chunks = a.autotune(1e30, steps_per_candidate=2)
+    assert len(chunks) == 1 and 4 <= chunks[0] <= w.ny
+    n_tune = int(a.times(0)[1][0])
+    a.step(1e30, 40 - n_tune)
+    b = vlbm.Ensemble(vlbm.Params.jet(), [(w.nx, w.ny, w.dx, w.y_min)], coefs, R)
+    b.tune("reference", 0)
+    b.step(1e30, 40)
+    sa, sb = a.state(0).cpu().numpy(), b.state(0).cpu().numpy()
+    assert np.array_equal(sa, sb)
+    c = vlbm.Ensemble(vlbm.Params.jet(), [(w.nx, w.ny, w.dx, w.y_min)], coefs, R)
+    c.step(1e30, 40)
+    assert np.array_equal(c.state(0).cpu().numpy(), sa)
+    for e in (a, b, c):
+        e.close()
