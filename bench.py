@@ -2,6 +2,11 @@
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--precision fp64|mixed]
 
+By default both storage precisions run: the FP64 pipeline gives the headline
+value and the mixed one (populations' rho, rho v in FP32) is reported beside it,
+with its speedup and the mean/std/W1 errors of its final ensemble against the
+FP64 ensemble of the same run.
+
 One benchmark step is one pass of the whole hot path over one ensemble of
 synthetic realizations of the jet workload (640 x 320 nodes, M = 64, to
 t = 1e-3): initial datum, time stepping (fused collide-stream kernel with the
@@ -13,7 +18,7 @@ run-to-run determinism check).
 
 Prints one JSON line.  `value` is ensemble GLUPS: node updates summed over
 realizations per second of the whole step.  `roofline` reports the step
-kernel: algorithmic 320 B per FP64 node update (200 B mixed) over its average
+kernel: algorithmic 320 B per FP64 node update (224 B mixed) over its average
 launch duration, measured with HIP events on the stream the kernels run on.
 `cpu_baseline` times the CPU oracle on a bounded sample on this host.
 """
@@ -31,7 +36,9 @@ sys.path.insert(0, ROOT)
 
 METRIC = "ensemble GLUPS (cell-updates/s summed over realizations) + % HBM roofline, FP64 vs mixed"
 HBM_PEAK_GBS = 8000.0
-BYTES_PER_LUP = {"fp64": 320.0, "mixed": 200.0}
+# algorithmic bytes per node update: 20 values read + 20 written; the mixed
+# variant stores the populations' rho, rho v in FP32 (112 B per node)
+BYTES_PER_LUP = {"fp64": 320.0, "mixed": 224.0}
 
 
 def kernel_source_hash() -> str:
@@ -86,7 +93,7 @@ def main() -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
+    ap.add_argument("--precision", default="both", choices=["both", "fp64", "mixed"])
     ap.add_argument("--workload", default="jet640")
     ap.add_argument("--chunk", type=int, default=240, help="launches per vlbm_step call")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -112,25 +119,21 @@ def main() -> int:
     vlbm.lib()  # fails loudly if the HIP library was not built
     w = inputs.WORKLOADS[args.workload]
     R, r_stats, r_w1 = w.m, 1, 2
-    params = vlbm.Params.jet(precision=args.precision)
     coefs = inputs.kl_coefficients(inputs.DEFAULT_SEED, 0, R)
     stream = torch.cuda.current_stream()
     ncell = w.nx * w.ny
     ncell_w1 = (w.nx // r_w1) * (w.ny // r_w1)
-    acc = torch.empty((3, 2, ncell), dtype=torch.float64, device="cuda")
-    mean = torch.empty((3, ncell), dtype=torch.float64, device="cuda")
-    std = torch.empty_like(mean)
-    sacc = torch.empty((3, 2, ncell_w1), dtype=torch.float64, device="cuda")
-    samples = [torch.empty((R, ncell_w1), dtype=torch.float64, device="cuda") for _ in range(2)]
-    w1c = torch.empty(ncell_w1, dtype=torch.float64, device="cuda")
-    w1m = torch.zeros(1, dtype=torch.float64, device="cuda")
-    # the ensemble's state buffers are allocated once and reused by every step
-    nbytes = vlbm.vlbm_state_bytes(params, w.nx, w.ny, R)
-    bufs = [torch.empty(nbytes, dtype=torch.uint8, device="cuda") for _ in range(2)]
-    level = vlbm.Level(w.nx, w.ny, w.dx, w.y_min,
-                       (vlbm._VP * 2)(bufs[0].data_ptr(), bufs[1].data_ptr()))
+
+    def make_level(params):
+        nbytes = vlbm.vlbm_state_bytes(params, w.nx, w.ny, R)
+        bufs = [torch.empty(nbytes, dtype=torch.uint8, device="cuda") for _ in range(2)]
+        lv = vlbm.Level(w.nx, w.ny, w.dx, w.y_min,
+                        (vlbm._VP * 2)(bufs[0].data_ptr(), bufs[1].data_ptr()))
+        return lv, bufs
 
     if args.profile_launches > 0:
+        params = vlbm.Params.jet(precision=args.precision if args.precision != "both" else "fp64")
+        level, bufs = make_level(params)
         h = vlbm.vlbm_init_ensemble(params, [level], coefs, R, stream)
         vlbm.vlbm_step(h, w.t_final, args.profile_launches, want_done=True)
         vlbm.vlbm_destroy(h)
@@ -142,87 +145,137 @@ def main() -> int:
               f"({R} x {w.nx} x {w.ny}) and one 2 GiB copy", flush=True)
         return 0
 
-    # Autotune the step kernel on live steps of a first ensemble (outside the timed
-    # region); later ensembles of the same shape reuse the cached choice.
-    h = vlbm.vlbm_init_ensemble(params, [level], coefs, R, stream)
-    tuned_chunks = vlbm.vlbm_autotune(h, w.t_final, 4, 1)
-    vlbm.vlbm_destroy(h)
+    def run_variant(precision: str, first_seed: int = 0, timed_steps=None, warmup=None, tune=True):
+        params = vlbm.Params.jet(precision=precision)
+        coefs = inputs.kl_coefficients(inputs.DEFAULT_SEED, first_seed, R)
+        level, bufs = make_level(params)
+        acc = torch.empty((3, 2, ncell), dtype=torch.float64, device="cuda")
+        mean = torch.empty((3, ncell), dtype=torch.float64, device="cuda")
+        std = torch.empty_like(mean)
+        sacc = torch.empty((3, 2, ncell_w1), dtype=torch.float64, device="cuda")
+        samples = [torch.empty((R, ncell_w1), dtype=torch.float64, device="cuda") for _ in range(2)]
+        w1c = torch.empty(ncell_w1, dtype=torch.float64, device="cuda")
+        w1m = torch.zeros(1, dtype=torch.float64, device="cuda")
+        # Autotune on live steps of a first ensemble (outside the timed region);
+        # later ensembles of the same shape reuse the cached choice.
+        tuned = [0]
+        if tune:
+            h = vlbm.vlbm_init_ensemble(params, [level], coefs, R, stream)
+            tuned = vlbm.vlbm_autotune(h, w.t_final, 4, 1)
+            vlbm.vlbm_destroy(h)
+        n_timed = args.steps if timed_steps is None else timed_steps
+        n_warm = args.warmup if warmup is None else warmup
+        step_ms, step_launches, totals = [0.0], [0], {"lups": 0.0}
+        last = {}
 
-    step_ms, step_launches = [0.0], [0]
-    totals = {"lups": 0.0}
-
-    def one_step(k: int, timed: bool):
-        h = vlbm.vlbm_init_ensemble(params, [level], coefs, R, stream)
-        done = False
-        while not done:
+        def one_step(k: int, timed: bool):
+            h = vlbm.vlbm_init_ensemble(params, [level], coefs, R, stream)
+            done = False
+            while not done:
+                if timed:
+                    e0 = torch.cuda.Event(enable_timing=True)
+                    e1 = torch.cuda.Event(enable_timing=True)
+                    e0.record(stream)
+                done = vlbm.vlbm_step(h, w.t_final, args.chunk, want_done=True)
+                if timed:
+                    e1.record(stream)
+                    e1.synchronize()
+                    step_ms[0] += e0.elapsed_time(e1)
+                    step_launches[0] += args.chunk
+            t, s, a, status = vlbm.vlbm_times(h, 0, R)
+            vlbm.vlbm_ensemble_stats(h, 0, r_stats, acc, 0, None, 0)
+            vlbm.vlbm_stats_finalize(acc, ncell, R, mean, std, stream)
+            cur, prev = samples[k % 2], samples[(k + 1) % 2]
+            vlbm.vlbm_ensemble_stats(h, 0, r_w1, sacc, 0, cur, 0)
+            vlbm.vlbm_sort_samples(cur, ncell_w1, R, stream)
+            if k > 0:
+                vlbm.vlbm_w1(cur, prev, ncell_w1, R, w1c, w1m, stream)
+            vlbm.vlbm_destroy(h)
             if timed:
-                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-                e0.record(stream)
-            done = vlbm.vlbm_step(h, w.t_final, args.chunk, want_done=True)
-            if timed:
-                e1.record(stream)
-                e1.synchronize()
-                step_ms[0] += e0.elapsed_time(e1)
-                step_launches[0] += args.chunk
-        t, s, a, status = vlbm.vlbm_times(h, 0, R)
-        vlbm.vlbm_ensemble_stats(h, 0, r_stats, acc, 0, None, 0)
-        vlbm.vlbm_stats_finalize(acc, ncell, R, mean, std, stream)
-        cur, prev = samples[k % 2], samples[(k + 1) % 2]
-        vlbm.vlbm_ensemble_stats(h, 0, r_w1, sacc, 0, cur, 0)
-        vlbm.vlbm_sort_samples(cur, ncell_w1, R, stream)
-        if k > 0:
-            vlbm.vlbm_w1(cur, prev, ncell_w1, R, w1c, w1m, stream)
-        vlbm.vlbm_destroy(h)
-        if timed:
-            totals["lups"] += float(s.sum()) * w.nx * w.ny
-        return s, t
+                totals["lups"] += float(s.sum()) * w.nx * w.ny
+            last["steps"], last["sorted"] = s, cur
+            return s
 
-    for k in range(args.warmup):
-        one_step(k, False)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    last_steps = None
-    for k in range(args.steps):
-        last_steps, t_end = one_step(args.warmup + k, True)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-
-    w1_check = float(w1m.item()) if args.warmup + args.steps > 1 else None
-    value = totals["lups"] / elapsed / 1e9
-    # Step-kernel roofline: launches in the timed chunks (graph or eager) vs events.
-    lup_per_step_pass = float(last_steps.sum()) * w.nx * w.ny
-    launches_per_pass = step_launches[0] / max(args.steps, 1)
-    avg_launch_ms = step_ms[0] / max(step_launches[0], 1)
-    bytes_pass = BYTES_PER_LUP[args.precision] * lup_per_step_pass
-    achieved = bytes_pass / (step_ms[0] / args.steps / 1e3) / 1e9
-    traffic = measured_traffic(args.precision)
-    if args.copy_probe:
-        a = torch.empty(1 << 28, dtype=torch.float64, device="cuda")
-        b = torch.empty_like(a)
-        b.copy_(a)
+        for k in range(n_warm):
+            one_step(k, False)
         torch.cuda.synchronize()
-        del a, b
+        t0 = time.perf_counter()
+        for k in range(n_timed):
+            one_step(n_warm + k, True)
+        torch.cuda.synchronize()
+        elapsed = time.perf_counter() - t0
+        steps_r = last["steps"]
+        lup_pass = float(steps_r.sum()) * w.nx * w.ny
+        achieved = (BYTES_PER_LUP[precision] * lup_pass / (step_ms[0] / n_timed / 1e3) / 1e9
+                    if step_ms[0] > 0 else 0.0)
+        return {
+            "value": totals["lups"] / elapsed / 1e9 if n_timed > 0 else 0.0,
+            "ms_per_step": elapsed / max(n_timed, 1) * 1e3,
+            "achieved": achieved,
+            "avg_launch_ms": step_ms[0] / max(step_launches[0], 1),
+            "launches_per_pass": step_launches[0] / max(n_timed, 1),
+            "tuned_rows": tuned[0],
+            "steps": [int(steps_r.min()), int(steps_r.max())],
+            "w1_rerun": float(w1m.item()) if n_warm + n_timed > 1 else None,
+            "mean": mean.clone(), "std": std.clone(), "sorted": last["sorted"].clone(),
+        }
+
+    variants = ["fp64", "mixed"] if args.precision == "both" else [args.precision]
+    res = {v: run_variant(v) for v in variants}
+    head = variants[0]
+    r0 = res[head]
     out = {
-        "metric": METRIC, "value": round(value, 4), "unit": "GLUPS", "n_gpus": 1,
+        "metric": METRIC, "value": round(r0["value"], 4), "unit": "GLUPS", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup,
-        "ms_per_step": round(elapsed / args.steps * 1e3, 3), "higher_is_better": True,
+        "ms_per_step": round(r0["ms_per_step"], 3), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None,
-        "dtype": "f64" if args.precision == "fp64" else "f32+f64",
+        "dtype": "f64" if head == "fp64" else "f32+f64",
         "data": "synthetic",
         "config": {"workload": f"{w.name}: Mach-2000 jet, {w.nx}x{w.ny} nodes on [0,1]x[-0.25,0.25], "
-                               f"M={R} realizations to t={w.t_final:g}, {args.precision}",
-                   "precision": args.precision, "nx": w.nx, "ny": w.ny, "realizations": R,
+                               f"M={R} realizations to t={w.t_final:g}, {head}",
+                   "precision": head, "nx": w.nx, "ny": w.ny, "realizations": R,
                    "t_final": w.t_final, "seed": inputs.DEFAULT_SEED,
-                   "time_steps_per_realization": [int(last_steps.min()), int(last_steps.max())],
-                   "step_kernel_rows_per_wave": tuned_chunks[0]},
-        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": traffic,
-                     "kernel": "vlbm step kernel", "bytes_per_node_update": BYTES_PER_LUP[args.precision],
-                     "avg_launch_ms": round(avg_launch_ms, 5),
-                     "launches_per_pass": launches_per_pass},
-        "w1_rerun": w1_check,
+                   "time_steps_per_realization": r0["steps"],
+                   "step_kernel_rows_per_wave": r0["tuned_rows"]},
+        "roofline": {"bound": "hbm", "achieved": round(r0["achieved"], 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(r0["achieved"] / HBM_PEAK_GBS, 4),
+                     "traffic": measured_traffic(head),
+                     "kernel": "vlbm step kernel", "bytes_per_node_update": BYTES_PER_LUP[head],
+                     "avg_launch_ms": round(r0["avg_launch_ms"], 5),
+                     "launches_per_pass": r0["launches_per_pass"]},
+        "w1_rerun": r0["w1_rerun"],
     }
+    def stat_errors(a, b):
+        """mean/std rel. L1 per field and W1 / mean density between two runs' final
+        ensembles (a is the reference)."""
+        rel = lambda x, y: float((x - y).abs().sum() / y.abs().sum())
+        w1c = torch.empty(ncell_w1, dtype=torch.float64, device="cuda")
+        w1m = torch.zeros(1, dtype=torch.float64, device="cuda")
+        vlbm.vlbm_w1(a["sorted"], b["sorted"], ncell_w1, R, w1c, w1m, stream)
+        torch.cuda.synchronize()
+        return {"mean_rel_l1": [round(rel(b["mean"][f], a["mean"][f]), 9) for f in range(3)],
+                "std_rel_l1": [round(rel(b["std"][f], a["std"][f]), 9) for f in range(3)],
+                "w1_over_mean_rho": round(float(w1m.item()) / float(a["mean"][0].mean()), 9),
+                "fields": ["rho", "|v|", "p"]}
+
+    if "mixed" in res and head == "fp64":
+        rm = res["mixed"]
+        # sampling-noise scale: an independent FP64 ensemble (the next R seeds)
+        other = run_variant("fp64", first_seed=R, timed_steps=0, warmup=1, tune=False)
+        out["mixed"] = {
+            "value": round(rm["value"], 4), "unit": "GLUPS", "dtype": "f32+f64",
+            "ms_per_step": round(rm["ms_per_step"], 3),
+            "speedup_vs_fp64": round(rm["value"] / r0["value"], 4),
+            "roofline": {"bound": "hbm", "achieved": round(rm["achieved"], 1), "peak": HBM_PEAK_GBS,
+                         "unit": "GB/s", "frac": round(rm["achieved"] / HBM_PEAK_GBS, 4),
+                         "traffic": measured_traffic("mixed"),
+                         "bytes_per_node_update": BYTES_PER_LUP["mixed"],
+                         "avg_launch_ms": round(rm["avg_launch_ms"], 5)},
+            "error_vs_fp64": stat_errors(res["fp64"], rm),
+            "fp64_independent_ensemble_difference": stat_errors(res["fp64"], other),
+            "time_steps_per_realization": rm["steps"],
+            "step_kernel_rows_per_wave": rm["tuned_rows"],
+        }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w)
     print(json.dumps(out), flush=True)

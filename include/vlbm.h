@@ -39,8 +39,11 @@
  * vlbm_state_bytes() each are needed per level; which one holds a given
  * realization's current state depends on its step count, so read states only
  * through vlbm_get_state, vlbm_moments or vlbm_ensemble_stats.
- * With VLBM_MIXED the rho, rho v1, rho v2 planes (all 5 slots) are stored
- * as FP32 first, followed by the E planes in FP64; all arithmetic is FP64.
+ * With VLBM_MIXED the populations' rho, rho v1, rho v2 planes are stored in
+ * FP32 and everything else in FP64: the buffer holds double u[4 var][R][ny][nx],
+ * then double E_k[4 slot][R][ny][nx], then float q[3 var][4 slot][R][ny][nx]
+ * (112 B per node).  All arithmetic, the pressure recovery and the
+ * admissibility check are FP64.
  */
 #ifndef VLBM_H
 #define VLBM_H
@@ -77,7 +80,7 @@ typedef int32_t vlbm_status;
 
 /* Storage precision of the state. */
 #define VLBM_FP64 0
-#define VLBM_MIXED 1 /* rho and rho v planes FP32, E planes FP64 */
+#define VLBM_MIXED 1 /* population rho, rho v planes FP32; u and E populations FP64 */
 
 typedef struct vlbm_params {
     double gamma;      /* heat-capacity ratio, eq:eos (5/3)                       */

@@ -30,6 +30,7 @@ _LIB = os.path.join(_HERE, "libvlbm_oracle.so")
 
 BC = {"jet": 0, "periodic": 1, "neumann": 2}
 THETA = {"limiter": 0, "zero": 1, "one": 2, "given": 3}
+STORAGE = {"fp64": 0, "mixed": 1}
 OK, ERR_ARG, ERR_NONPOSITIVE, ERR_NONFINITE = 0, -1, -4, -5
 
 
@@ -53,7 +54,7 @@ class _Params(ctypes.Structure):
                 ("v_jet", ctypes.c_double), ("r_jet", ctypes.c_double),
                 ("kl_amp", ctypes.c_double), ("kl_modes", ctypes.c_int32),
                 ("kl_decay", ctypes.c_int32), ("bc", ctypes.c_int32),
-                ("theta_mode", ctypes.c_int32)]
+                ("theta_mode", ctypes.c_int32), ("storage", ctypes.c_int32)]
 
 
 class _Grid(ctypes.Structure):
@@ -79,12 +80,13 @@ class Params:
     kl_modes: int = 10
     bc: str = "jet"
     theta_mode: str = "limiter"
+    storage: str = "fp64"
 
     def c(self) -> _Params:
         return _Params(self.gamma, self.alpha, self.kappa, self.rlmp_relax, self.pos_eps,
                        self.rho_amb, self.p_amb, self.rho_jet, self.v_jet, self.r_jet,
                        self.kl_amp, self.kl_modes, self.kl_decay, BC[self.bc],
-                       THETA[self.theta_mode])
+                       THETA[self.theta_mode], STORAGE[self.storage])
 
 
 @dataclass

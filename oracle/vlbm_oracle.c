@@ -65,6 +65,7 @@ typedef struct {
     int32_t kl_decay;   /* p of eq:karhunenExp (a non-negative integer)       */
     int32_t bc;         /* ORC_BC_JET, ORC_BC_PERIODIC, ORC_BC_NEUMANN        */
     int32_t theta_mode; /* ORC_THETA_LIMITER, _ZERO, _ONE, _GIVEN             */
+    int32_t storage;    /* ORC_STORE_FP64, ORC_STORE_MIXED                    */
 } orc_params;
 
 typedef struct {
@@ -76,6 +77,11 @@ typedef struct {
 enum { ORC_BC_JET = 0, ORC_BC_PERIODIC = 1, ORC_BC_NEUMANN = 2 };
 enum { ORC_THETA_LIMITER = 0, ORC_THETA_ZERO = 1, ORC_THETA_ONE = 2, ORC_THETA_GIVEN = 3 };
 enum { ORC_OK = 0, ORC_ERR_ARG = -1, ORC_ERR_NONPOSITIVE = -4, ORC_ERR_NONFINITE = -5 };
+/* Storage of the state between steps.  ORC_STORE_MIXED is the mixed-precision
+ * variant (not in the paper): the rho, rho v1, rho v2 components of the
+ * populations u_1..u_4 are held in binary32; the macroscopic u and the energy
+ * populations stay binary64, and all arithmetic is binary64. */
+enum { ORC_STORE_FP64 = 0, ORC_STORE_MIXED = 1 };
 
 #define ST(st, s, v, j, i) (st)[((size_t)((s) * 4 + (v)) * (size_t)G->ny + (size_t)(j)) * (size_t)G->nx + (size_t)(i)]
 
@@ -224,6 +230,18 @@ double orc_kinetic_speed(const orc_params *P, const orc_grid *G, const double *s
     return P->kappa * 2.0 * smax / (1.0 - P->alpha);
 }
 
+/* Round the stored populations to the storage precision (ORC_STORE_MIXED). */
+static void store_round(const orc_params *P, const orc_grid *G, double *st)
+{
+    if (P->storage != ORC_STORE_MIXED)
+        return;
+    for (int s = 1; s <= 4; ++s)
+        for (int v = 0; v < 3; ++v)
+            for (int j = 0; j < G->ny; ++j)
+                for (int i = 0; i < G->nx; ++i)
+                    ST(st, s, v, j, i) = (double)(float)ST(st, s, v, j, i);
+}
+
 /* Populations at equilibrium with the macroscopic state, u_k = M_k(u; a)
  * (reading R7). */
 void orc_fill_equilibrium(const orc_params *P, const orc_grid *G, double a, double *st)
@@ -238,6 +256,7 @@ void orc_fill_equilibrium(const orc_params *P, const orc_grid *G, double a, doub
                 for (int v = 0; v < 4; ++v)
                     ST(st, 1 + k, v, j, i) = M[k * 4 + v];
         }
+    store_round(P, G, st);
 }
 
 /* Initial datum of eq:u0_def for one realization: u_inlet on column 0,
@@ -540,6 +559,8 @@ int orc_step(const orc_params *P, const orc_grid *G, double a, const double *st,
                         ST(st_new, s, v, j, i) = ST(st_new, s, v, js, is);
             }
         }
+
+    store_round(P, G, st_new);
 
     /* Admissibility of the new state. */
     int status = ORC_OK;

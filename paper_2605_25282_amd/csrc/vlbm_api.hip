@@ -76,8 +76,9 @@ size_t state_bytes(int prec, int nx, int ny, int R)
     const size_t plane = (size_t)nx * (size_t)ny;
     if (prec == VLBM_FP64)
         return (size_t)20 * (size_t)R * plane * sizeof(double);
-    const size_t fbytes = ((size_t)15 * (size_t)R * plane * sizeof(float) + 255) & ~(size_t)255;
-    return fbytes + (size_t)5 * (size_t)R * plane * sizeof(double);
+    // FP64: u (4 planes) and the E populations (4 planes); FP32: rho, rho v1, rho v2
+    // populations (12 planes) -- 112 B per node
+    return (size_t)8 * (size_t)R * plane * sizeof(double) + (size_t)12 * (size_t)R * plane * sizeof(float);
 }
 
 vlbm_status check_params(const vlbm_params *p)

@@ -328,53 +328,82 @@ struct StateFP64 {
         return (const char *)(p + ((size_t)(v * 5 + s) * (size_t)R + (size_t)m) * plane);
     }
     __device__ __forceinline__ char *plane_w(int v, int s, int m) const { return (char *)plane_base(v, s, m); }
-    __device__ static __forceinline__ unsigned esize(int) { return 8u; }
-    __device__ static __forceinline__ double ldp(const char *base, int, unsigned off)
+    __device__ static __forceinline__ unsigned esize(int, int) { return 8u; }
+    __device__ static __forceinline__ double ldp(const char *base, int, int, unsigned off)
     {
         return *(const double *)(base + off);
     }
-    __device__ static __forceinline__ void stp(char *base, int, unsigned off, double x) { *(double *)(base + off) = x; }
+    __device__ static __forceinline__ void stp(char *base, int, int, unsigned off, double x)
+    {
+        *(double *)(base + off) = x;
+    }
+    // Raw element bits for prefetching: the conversion to double happens at the
+    // point of use, so a load in flight is not waited for at the loop back-edge.
+    __device__ static __forceinline__ unsigned long long ldraw(const char *base, int, int, unsigned off)
+    {
+        return *(const unsigned long long *)(base + off);
+    }
+    __device__ static __forceinline__ double decode(int, int, unsigned long long r) { return __longlong_as_double((long long)r); }
 };
 
 struct StateMixed {
-    float *pf;   // var 0..2
-    double *pd;  // var 3
+    // FP64 part: slot 0 (u, 4 variables) then the E planes of slots 1..4;
+    // FP32 part: rho, rho v1, rho v2 planes of the populations (slots 1..4).
+    typedef double elem;
+    double *pd;
+    float *pf;
     size_t plane;
     int R;
+    __device__ __forceinline__ bool is_f32(int v, int s) const { return s > 0 && v < 3; }
+    __device__ __forceinline__ size_t d_index(int v, int s) const { return s == 0 ? (size_t)v : (size_t)(3 + s); }
+    __device__ __forceinline__ size_t f_index(int v, int s) const { return (size_t)(v * 4 + (s - 1)); }
     __device__ __forceinline__ double ld(int v, int s, int m, size_t node) const
     {
-        if (v < 3)
-            return (double)pf[((size_t)(v * 5 + s) * (size_t)R + (size_t)m) * plane + node];
-        return pd[((size_t)s * (size_t)R + (size_t)m) * plane + node];
+        if (is_f32(v, s))
+            return (double)pf[(f_index(v, s) * (size_t)R + (size_t)m) * plane + node];
+        return pd[(d_index(v, s) * (size_t)R + (size_t)m) * plane + node];
     }
     __device__ __forceinline__ void st(int v, int s, int m, size_t node, double x) const
     {
-        if (v < 3)
-            pf[((size_t)(v * 5 + s) * (size_t)R + (size_t)m) * plane + node] = (float)x;
+        if (is_f32(v, s))
+            pf[(f_index(v, s) * (size_t)R + (size_t)m) * plane + node] = (float)x;
         else
-            pd[((size_t)s * (size_t)R + (size_t)m) * plane + node] = x;
+            pd[(d_index(v, s) * (size_t)R + (size_t)m) * plane + node] = x;
     }
-    __device__ __forceinline__ double stored(int v, double x) const { return v < 3 ? (double)(float)x : x; }
+    // the macroscopic slot is FP64, so a stored u reads back unchanged
+    __device__ __forceinline__ double stored(int, double x) const { return x; }
     __device__ __forceinline__ const char *plane_base(int v, int s, int m) const
     {
-        if (v < 3)
-            return (const char *)(pf + ((size_t)(v * 5 + s) * (size_t)R + (size_t)m) * plane);
-        return (const char *)(pd + ((size_t)s * (size_t)R + (size_t)m) * plane);
+        if (is_f32(v, s))
+            return (const char *)(pf + (f_index(v, s) * (size_t)R + (size_t)m) * plane);
+        return (const char *)(pd + (d_index(v, s) * (size_t)R + (size_t)m) * plane);
     }
     __device__ __forceinline__ char *plane_w(int v, int s, int m) const { return (char *)plane_base(v, s, m); }
-    __device__ static __forceinline__ unsigned esize(int v) { return v < 3 ? 4u : 8u; }
-    __device__ static __forceinline__ double ldp(const char *base, int v, unsigned off)
+    __device__ static __forceinline__ unsigned esize(int v, int s) { return (s > 0 && v < 3) ? 4u : 8u; }
+    __device__ static __forceinline__ double ldp(const char *base, int v, int s, unsigned off)
     {
-        if (v < 3)
+        if (s > 0 && v < 3)
             return (double)*(const float *)(base + off);
         return *(const double *)(base + off);
     }
-    __device__ static __forceinline__ void stp(char *base, int v, unsigned off, double x)
+    __device__ static __forceinline__ void stp(char *base, int v, int s, unsigned off, double x)
     {
-        if (v < 3)
+        if (s > 0 && v < 3)
             *(float *)(base + off) = (float)x;
         else
             *(double *)(base + off) = x;
+    }
+    __device__ static __forceinline__ unsigned long long ldraw(const char *base, int v, int s, unsigned off)
+    {
+        if (s > 0 && v < 3)
+            return (unsigned long long)*(const unsigned int *)(base + off);
+        return *(const unsigned long long *)(base + off);
+    }
+    __device__ static __forceinline__ double decode(int v, int s, unsigned long long r)
+    {
+        if (s > 0 && v < 3)
+            return (double)__uint_as_float((unsigned int)r);
+        return __longlong_as_double((long long)r);
     }
 };
 
@@ -405,8 +434,8 @@ template <> struct StateOf<1> {
     typedef StateMixed type;
     __device__ static type make(void *b, size_t plane, int R)
     {
-        const size_t fbytes = (((size_t)15 * (size_t)R * plane * sizeof(float)) + 255) & ~(size_t)255;
-        return StateMixed{(float *)b, (double *)((char *)b + fbytes), plane, R};
+        const size_t dbytes = (size_t)8 * (size_t)R * plane * sizeof(double);
+        return StateMixed{(double *)b, (float *)((char *)b + dbytes), plane, R};
     }
 };
 

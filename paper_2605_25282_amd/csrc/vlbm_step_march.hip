@@ -162,15 +162,15 @@ step_march_kernel(PhysArgs ph, LevelArgs L, Ctl ctl, int phase, double t_final, 
             return true;
         return kind_col_interior && j >= 1 && j <= ny - 2;
     };
-    auto off_of = [&](int j, int col, int v) -> unsigned {
-        return (unsigned)((size_t)j * nx + col) * St::esize(v);
+    auto off_of = [&](int j, int col, int v, int sl) -> unsigned {
+        return (unsigned)((size_t)j * nx + col) * St::esize(v, sl);
     };
     double wmax = 0.0;
     int bad = 0;
     auto store_slot = [&](int sl, int j, const double x[4]) {
 #pragma unroll
         for (int v = 0; v < 4; ++v)
-            St::stp(out_plane(sl, v), v, off_of(j, c, v), x[v]);
+            St::stp(out_plane(sl, v), v, sl, off_of(j, c, v, sl), x[v]);
     };
     auto account = [&](const double u[4]) {
         double us[4];
@@ -207,7 +207,8 @@ step_march_kernel(PhysArgs ph, LevelArgs L, Ctl ctl, int phase, double t_final, 
     // north-face term, N_3 and M_3, the low-order state and its bounds.
     double U0[4], U1[4];
     double pC[4], cC[4], N3C[4], M3C[4], LC[4], bC[3];
-    double Un[4], Pn[4][4]; // loads in flight: U(k+1), populations of row k
+    double Un[4];               // load in flight: U(k+1)
+    unsigned long long Pn[4][4]; // loads in flight: populations of row k (raw element bits)
 
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
@@ -215,14 +216,14 @@ step_march_kernel(PhysArgs ph, LevelArgs L, Ctl ctl, int phase, double t_final, 
         pC[v] = cC[v] = N3C[v] = M3C[v] = LC[v] = 0.0;
 #pragma unroll
         for (int q = 0; q < 4; ++q)
-            Pn[q][v] = 0.0;
+            Pn[q][v] = 0ull;
     }
     bC[0] = bC[1] = bC[2] = 0.0;
 
     const int k_first = y0 - 2, k_last = y1 + 1;
 #pragma unroll
     for (int v = 0; v < 4; ++v)
-        Un[v] = St::ldp(inU[v], v, off_of(row_of(k_first), cx, v));
+        Un[v] = St::ldp(inU[v], v, 0, off_of(row_of(k_first), cx, v, 0));
 
     for (int k = k_first; k <= k_last; ++k) {
 #pragma unroll
@@ -235,13 +236,13 @@ step_march_kernel(PhysArgs ph, LevelArgs L, Ctl ctl, int phase, double t_final, 
         for (int q = 0; q < 4; ++q)
 #pragma unroll
             for (int v = 0; v < 4; ++v)
-                NB[q][v] = MB[q][v] - Pn[q][v];
+                NB[q][v] = MB[q][v] - St::decode(v, 1 + q, Pn[q][v]);
         // Issue the next loads: macroscopic row k+1 and population row k.
         if (k < k_last) {
             const int jr = row_of(k + 1);
 #pragma unroll
             for (int v = 0; v < 4; ++v)
-                Un[v] = St::ldp(inU[v], v, off_of(jr, cx, v));
+                Un[v] = St::ldp(inU[v], v, 0, off_of(jr, cx, v, 0));
         }
         if (k >= y0 - 1 && k <= y1) { // population row k is row k-1 of the next iteration
             const int jr = row_of(k);
@@ -249,7 +250,7 @@ step_march_kernel(PhysArgs ph, LevelArgs L, Ctl ctl, int phase, double t_final, 
             for (int q = 0; q < 4; ++q)
 #pragma unroll
                 for (int v = 0; v < 4; ++v)
-                    Pn[q][v] = St::ldp(inP[q][v], v, off_of(jr, cx, v));
+                    Pn[q][v] = St::ldraw(inP[q][v], v, 1 + q, off_of(jr, cx, v, 1 + q));
         }
 
         // Low-order state and bounds of row k-1.

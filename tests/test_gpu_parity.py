@@ -357,3 +357,79 @@ def test_autotune_is_result_neutral_and_cached():
     assert np.array_equal(c.state(0).cpu().numpy(), sa)
     for e in (a, b, c):
         e.close()
+
+
+@pytest.mark.parametrize("alpha", [0.0, 1.0 / 3.0])
+def test_mixed_precision_matches_mixed_oracle(alpha):
+    """Mixed storage (populations' rho, rho v in FP32; u and E populations FP64;
+    all arithmetic FP64) against the oracle's mixed storage mode, 50 steps."""
+    w, g = _grid("jet128")
+    R, steps = 8, 50
+    coefs = inputs.kl_coefficients(inputs.DEFAULT_SEED, 0, R)
+    ens = vlbm.Ensemble(vlbm.Params.jet(alpha=alpha, precision="mixed"),
+                        [(w.nx, w.ny, w.dx, w.y_min)], coefs, R)
+    ens.step(1e30, steps)
+    st = ens.state(0).cpu().numpy()
+    ens.close()
+    p = O.Params(alpha=alpha, storage="mixed")
+    worst = 0.0
+    for m in range(R):
+        ref, _, n, _, rc = O.run(p, g, O.init(p, g, coefs[m]), 1e30, max_steps=steps)
+        assert rc == O.OK and n == steps
+        worst = max(worst, _plane_err(_to_oracle(st, m), ref))
+    print(f"mixed alpha={alpha}: worst plane rel err {worst:.3e}")
+    assert worst <= TOL
+
+
+@pytest.mark.parametrize("bc,nx,ny,chunk", [("jet", 128, 64, 0), ("jet", 121, 37, 16),
+                                            ("neumann", 61, 33, 8), ("periodic", 70, 37, 16)])
+def test_mixed_march_equals_reference(bc, nx, ny, chunk):
+    R, steps, gamma = 3, 25, (5.0 / 3.0 if bc == "jet" else 1.4)
+    coefs = inputs.kl_coefficients(inputs.DEFAULT_SEED, 0, R)
+    out = {}
+    for kern in ("reference", "march"):
+        kw = dict(bc=bc, gamma=gamma, precision="mixed")
+        if bc != "jet":
+            kw["kl_modes"] = 0
+        ens = vlbm.Ensemble(vlbm.Params.jet(**kw), [(nx, ny, 1.0 / nx, -0.5 * ny / nx)],
+                            coefs if bc == "jet" else None, R)
+        ens.tune(kern, chunk)
+        if bc != "jet":
+            ens.set_macroscopic(0, torch.tensor(_loaded_state(bc, nx, ny, R, gamma), device="cuda"))
+        ens.step(1e30, steps)
+        out[kern] = ens.state(0).cpu().numpy()
+        ens.close()
+    assert np.array_equal(out["reference"], out["march"])
+
+
+def test_mixed_vs_fp64_statistics_gpu():
+    """The mixed variant's ensemble statistics against the FP64 run on the GPU at the
+    final time of the 128 x 64 workload: mean/std (rel. L1) and W1 / mean density."""
+    w = inputs.WORKLOADS["jet128"]
+    R = w.m
+    coefs = inputs.kl_coefficients(inputs.DEFAULT_SEED, 0, R)
+    ncell = w.nx * w.ny
+    res = {}
+    for prec in ("fp64", "mixed"):
+        ens = vlbm.Ensemble(vlbm.Params.jet(precision=prec), [(w.nx, w.ny, w.dx, w.y_min)], coefs, R)
+        ens.run(w.t_final, chunk=16)
+        acc = torch.empty((3, 2, ncell), dtype=torch.float64, device="cuda")
+        smp = torch.empty((R, ncell), dtype=torch.float64, device="cuda")
+        vlbm.vlbm_ensemble_stats(ens.h, 0, 1, acc, 0, smp, 0)
+        mean = torch.empty((3, ncell), dtype=torch.float64, device="cuda")
+        std = torch.empty_like(mean)
+        vlbm.vlbm_stats_finalize(acc, ncell, R, mean, std)
+        vlbm.vlbm_sort_samples(smp, ncell, R)
+        res[prec] = (mean, std, smp)
+        ens.close()
+    w1c = torch.empty(ncell, dtype=torch.float64, device="cuda")
+    w1m = torch.empty(1, dtype=torch.float64, device="cuda")
+    vlbm.vlbm_w1(res["fp64"][2], res["mixed"][2], ncell, R, w1c, w1m)
+    torch.cuda.synchronize()
+    m64, s64 = res["fp64"][0].cpu().numpy(), res["fp64"][1].cpu().numpy()
+    mmx, smx = res["mixed"][0].cpu().numpy(), res["mixed"][1].cpu().numpy()
+    em = _rel_l1(mmx, m64)
+    es = _rel_l1(smx, s64)
+    ew = w1m.item() / m64[0].mean()
+    print(f"mixed vs fp64: mean {em:.3e}, std {es:.3e}, W1/mean(rho) {ew:.3e}")
+    assert em < 1e-3 and es < 1e-3 and ew < 1e-3

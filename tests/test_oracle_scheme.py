@@ -273,3 +273,25 @@ def test_initial_populations_at_equilibrium():
     for j in range(g.ny):
         assert np.array_equal(st[0:4, j, 0], O.inlet_state(p, y[j], coef))
     assert np.all(st[0, :, 1:] == p.rho_amb) and np.all(st[1:3, :, 1:] == 0.0)
+
+
+def test_mixed_storage_statistics_close_to_fp64():
+    """The mixed-storage variant (populations' rho, rho v in binary32) keeps the
+    ensemble statistics of the 128 x 64 workload within 1e-3 of FP64 storage
+    (rel. L1 of mean and std; W1 over the mean density), and stays admissible."""
+    w = inputs.WORKLOADS["jet128"]
+    g = O.Grid(w.nx, w.ny, w.dx, w.y_min)
+    coefs = inputs.kl_coefficients(inputs.DEFAULT_SEED, 0, w.m)
+    res = {}
+    for stor in ("fp64", "mixed"):
+        p = O.Params(storage=stor)
+        S, T, N, RC = O.run_ensemble(p, g, coefs, w.t_final)
+        assert np.all(RC == O.OK)
+        res[stor] = O.moments(p, S[:, 0:4])
+    for f in range(3):
+        a, b = res["fp64"][f], res["mixed"][f]
+        ma, mb = O.ensemble_mean(a), O.ensemble_mean(b)
+        sa, sb = O.ensemble_std(a), O.ensemble_std(b)
+        assert np.abs(mb - ma).sum() / np.abs(ma).sum() < 1e-3
+        assert np.abs(sb - sa).sum() / np.abs(sa).sum() < 1e-3
+    assert O.w1(res["fp64"][0], res["mixed"][0]).mean() / O.ensemble_mean(res["fp64"][0]).mean() < 1e-3
