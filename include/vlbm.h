@@ -120,7 +120,7 @@ vlbm_status vlbm_state_bytes(const vlbm_params *p, int32_t nx, int32_t ny, int32
                              size_t *bytes);
 
 /*
- * Create an ensemble of n_real realizations on each of n_levels mesh levels
+ * Create an ensemble of n_real realizations on each of n_levels (1..8) mesh levels
  * and enqueue its initial datum (eq:u0_def, Sec. 2.2; populations at
  * equilibrium with the initial kinetic speed).
  *   coeffs: HOST array [n_real][2 * kl_modes]; row m holds the coefficients
@@ -148,7 +148,9 @@ vlbm_status vlbm_set_macroscopic(vlbm_ensemble *e, int32_t level, const double *
  * Advance every realization of every level by up to n_steps steps of
  * eq:vlbm1-eq:vlbm5, each realization stopping exactly at t_final (the last
  * steps are shortened, taking a = dx/dt).  Realizations already at t_final
- * are left untouched.  If all_done is non-NULL the call synchronizes the
+ * are left untouched.  One step of all levels is one kernel launch (work items
+ * of every level in one persistent grid); runs of 30 steps are replayed from a
+ * hipGraph captured once per t_final and configuration.  If all_done is non-NULL the call synchronizes the
  * stream, sets *all_done to 1 when every realization has reached t_final
  * (else 0), and returns VLBM_ERR_NONPOSITIVE / VLBM_ERR_NONFINITE if any
  * realization has latched a failure.
@@ -220,6 +222,8 @@ vlbm_status vlbm_w1(const double *sorted_a, const double *sorted_b, int64_t n_ce
 /* Step kernel implementations (vlbm_tune). */
 #define VLBM_KERNEL_REFERENCE 0 /* one thread per node, neighbours recomputed        */
 #define VLBM_KERNEL_MARCH 1     /* wavefront strips marching over rows (default)      */
+#define VLBM_KERNEL_NO_GRAPH 0x100 /* OR-ed flag: launch every step eagerly instead of
+                                      replaying captured hipGraphs of 30 steps       */
 
 /*
  * Select the step kernel and its work decomposition for this ensemble:

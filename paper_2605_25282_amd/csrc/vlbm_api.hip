@@ -25,9 +25,18 @@ template <int PREC> __global__ void init_macro_kernel(PhysArgs, LevelArgs, const
 template <int PREC> __global__ void equilibrium_kernel(PhysArgs, LevelArgs, Ctl, int);
 template <int PREC> __global__ void step_ref_kernel(PhysArgs, LevelArgs, Ctl, int, double);
 struct MarchArgs {
-    int nstrip, chunk, nchunk, nblocks, per_xcd, lane62_last;
+    int nstrip, chunk, nchunk, lane62_last;
 };
-template <int PREC> __global__ void step_march_kernel(PhysArgs, LevelArgs, Ctl, int, double, MarchArgs);
+static constexpr int MAX_LEVELS = 8;
+struct MultiLevel {
+    int nlev;
+    int nblocks;
+    int per_xcd;
+    long long item_off[MAX_LEVELS + 1];
+    LevelArgs L[MAX_LEVELS];
+    MarchArgs ma[MAX_LEVELS];
+};
+template <int PREC> __global__ void step_march_kernel(PhysArgs, MultiLevel, Ctl, int, double);
 template <int PREC> __global__ void moments_kernel(PhysArgs, LevelArgs, Ctl, int, double *, double *, double *);
 template <int PREC> __global__ void get_state_kernel(LevelArgs, Ctl, int, double *);
 template <int PREC> __global__ void set_macro_kernel(PhysArgs, LevelArgs, Ctl, const double *);
@@ -151,7 +160,15 @@ struct vlbm_ensemble {
     int n_cu = 256;         // compute units of the device
     int march_blocks_per_cu = 1;
     std::vector<int> level_chunk; // per-level chunk override (0 = from chunk_rows / model)
+    // hipGraph of GRAPH_STEPS consecutive steps (ring phases 0,1,2,...), captured on
+    // an internal stream and replayed on the ensemble's stream
+    bool use_graph = true;
+    hipStream_t cap_stream = nullptr;
+    hipGraphExec_t graph = nullptr;
+    double graph_t_final = 0.0;
 };
+
+static constexpr int GRAPH_STEPS = 30; // a multiple of 3 (the control ring's period)
 
 namespace {
 // Process-wide cache of tuned chunk heights.
@@ -193,7 +210,7 @@ int model_chunk(const vlbm_ensemble *e, const LevelArgs &L, int nstrip)
     return chunk < 16 ? 16 : chunk;
 }
 
-MarchArgs march_args(const vlbm_ensemble *e, int level, unsigned *grid)
+MarchArgs march_args(const vlbm_ensemble *e, int level)
 {
     const LevelArgs &L = e->levels[level];
     MarchArgs ma{};
@@ -207,32 +224,52 @@ MarchArgs march_args(const vlbm_ensemble *e, int level, unsigned *grid)
         chunk = L.ny;
     ma.chunk = chunk;
     ma.nchunk = (L.ny + chunk - 1) / chunk;
-    const long long waves = (long long)L.R * ma.nstrip * ma.nchunk;
-    long long blocks = (waves + 3) / 4;
-    const long long resident = (long long)e->n_cu * e->march_blocks_per_cu;
-    if (blocks > resident)
-        blocks = resident;
-    ma.nblocks = (int)blocks;
-    ma.per_xcd = (ma.nblocks + 7) / 8;
-    *grid = (unsigned)(8 * ma.per_xcd);
     return ma;
 }
 
-vlbm_status launch_step(vlbm_ensemble *e, const PhysArgs &ph, int level, int phase, double t_final)
+// One launch over levels [l0, l1): concatenated work items, grid sized to the
+// resident capacity, XCD-aware block numbering.
+MultiLevel multi_level(const vlbm_ensemble *e, int l0, int l1, unsigned *grid)
 {
-    const LevelArgs &L = e->levels[level];
+    MultiLevel ml{};
+    ml.nlev = l1 - l0;
+    ml.item_off[0] = 0;
+    for (int i = 0; i < ml.nlev; ++i) {
+        ml.L[i] = e->levels[l0 + i];
+        ml.ma[i] = march_args(e, l0 + i);
+        ml.item_off[i + 1] = ml.item_off[i] + (long long)ml.L[i].R * ml.ma[i].nstrip * ml.ma[i].nchunk;
+    }
+    long long blocks = (ml.item_off[ml.nlev] + 3) / 4;
+    const long long resident = (long long)e->n_cu * e->march_blocks_per_cu;
+    if (blocks > resident)
+        blocks = resident;
+    if (blocks < 1)
+        blocks = 1;
+    ml.nblocks = (int)blocks;
+    ml.per_xcd = (ml.nblocks + 7) / 8;
+    *grid = (unsigned)(8 * ml.per_xcd);
+    return ml;
+}
+
+// Enqueue one step of levels [l0, l1) on stream st.
+vlbm_status launch_step(vlbm_ensemble *e, const PhysArgs &ph, int l0, int l1, int phase, double t_final,
+                        hipStream_t st)
+{
     if (e->kernel == VLBM_KERNEL_REFERENCE) {
-        if (e->p.precision == VLBM_FP64)
-            step_ref_kernel<0><<<node_grid(L), 256, 0, e->stream>>>(ph, L, e->ctl, phase, t_final);
-        else
-            step_ref_kernel<1><<<node_grid(L), 256, 0, e->stream>>>(ph, L, e->ctl, phase, t_final);
+        for (int l = l0; l < l1; ++l) {
+            const LevelArgs &L = e->levels[l];
+            if (e->p.precision == VLBM_FP64)
+                step_ref_kernel<0><<<node_grid(L), 256, 0, st>>>(ph, L, e->ctl, phase, t_final);
+            else
+                step_ref_kernel<1><<<node_grid(L), 256, 0, st>>>(ph, L, e->ctl, phase, t_final);
+        }
     } else {
         unsigned grid = 0;
-        const MarchArgs ma = march_args(e, level, &grid);
+        const MultiLevel ml = multi_level(e, l0, l1, &grid);
         if (e->p.precision == VLBM_FP64)
-            step_march_kernel<0><<<grid, 256, 0, e->stream>>>(ph, L, e->ctl, phase, t_final, ma);
+            step_march_kernel<0><<<grid, 256, 0, st>>>(ph, ml, e->ctl, phase, t_final);
         else
-            step_march_kernel<1><<<grid, 256, 0, e->stream>>>(ph, L, e->ctl, phase, t_final, ma);
+            step_march_kernel<1><<<grid, 256, 0, st>>>(ph, ml, e->ctl, phase, t_final);
     }
     LAUNCH_CHECK("step");
     return VLBM_OK;
@@ -293,8 +330,8 @@ vlbm_status vlbm_init_ensemble(const vlbm_params *p, const vlbm_level *levels, i
     if (!out)
         return fail(VLBM_ERR_ARG, "out is NULL");
     *out = nullptr;
-    if (!levels || n_levels < 1 || n_levels > 16)
-        return fail(VLBM_ERR_ARG, "need 1..16 levels (got %d)", n_levels);
+    if (!levels || n_levels < 1 || n_levels > MAX_LEVELS)
+        return fail(VLBM_ERR_ARG, "need 1..%d levels (got %d)", MAX_LEVELS, n_levels);
     if (p->bc == VLBM_BC_JET && !coeffs && p->kl_modes > 0)
         return fail(VLBM_ERR_ARG, "coeffs is NULL for the jet problem");
     for (int l = 0; l < n_levels; ++l) {
@@ -452,6 +489,46 @@ vlbm_status vlbm_set_macroscopic(vlbm_ensemble *e, int32_t level, const double *
     return VLBM_OK;
 }
 
+namespace {
+void drop_graph(vlbm_ensemble *e)
+{
+    if (e->graph) {
+        (void)hipGraphExecDestroy(e->graph);
+        e->graph = nullptr;
+    }
+}
+
+// Capture GRAPH_STEPS steps (phases 0..GRAPH_STEPS-1 mod 3) into e->graph.
+vlbm_status capture_graph(vlbm_ensemble *e, double t_final)
+{
+    drop_graph(e);
+    if (!e->cap_stream)
+        HIP_TRY(hipStreamCreateWithFlags(&e->cap_stream, hipStreamNonBlocking));
+    const PhysArgs ph = phys_args(e->p);
+    HIP_TRY(hipStreamBeginCapture(e->cap_stream, hipStreamCaptureModeThreadLocal));
+    vlbm_status rc = VLBM_OK;
+    for (int s = 0; s < GRAPH_STEPS && rc == VLBM_OK; ++s)
+        rc = launch_step(e, ph, 0, (int)e->levels.size(), s % 3, t_final, e->cap_stream);
+    hipGraph_t g = nullptr;
+    hipError_t he = hipStreamEndCapture(e->cap_stream, &g);
+    if (rc != VLBM_OK) {
+        if (g)
+            (void)hipGraphDestroy(g);
+        return rc;
+    }
+    if (he != hipSuccess)
+        return fail(VLBM_ERR_HIP, "hipStreamEndCapture failed: %s", hipGetErrorString(he));
+    he = hipGraphInstantiate(&e->graph, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (he != hipSuccess) {
+        e->graph = nullptr;
+        return fail(VLBM_ERR_HIP, "hipGraphInstantiate failed: %s", hipGetErrorString(he));
+    }
+    e->graph_t_final = t_final;
+    return VLBM_OK;
+}
+} // namespace
+
 vlbm_status vlbm_step(vlbm_ensemble *e, double t_final, int32_t n_steps, int32_t *all_done)
 {
     if (!e)
@@ -461,14 +538,38 @@ vlbm_status vlbm_step(vlbm_ensemble *e, double t_final, int32_t n_steps, int32_t
     if (n_steps < 0)
         return fail(VLBM_ERR_ARG, "n_steps must be >= 0");
     const PhysArgs ph = phys_args(e->p);
-    for (int s = 0; s < n_steps; ++s) {
-        const int phase = phase_of(e);
-        for (int l = 0; l < (int)e->levels.size(); ++l) {
-            vlbm_status rc = launch_step(e, ph, l, phase, t_final);
+    int left = n_steps;
+    auto eager = [&](int n) -> vlbm_status {
+        for (int s = 0; s < n; ++s) {
+            vlbm_status rc = launch_step(e, ph, 0, (int)e->levels.size(), phase_of(e), t_final, e->stream);
+            if (rc != VLBM_OK)
+                return rc;
+            e->n_launch++;
+        }
+        return VLBM_OK;
+    };
+    if (e->use_graph && left >= GRAPH_STEPS + 2) {
+        // align the ring phase to 0, then replay whole graphs
+        const int lead = (int)((3 - e->n_launch % 3) % 3);
+        vlbm_status rc = eager(lead);
+        if (rc != VLBM_OK)
+            return rc;
+        left -= lead;
+        if (!e->graph || e->graph_t_final != t_final) {
+            rc = capture_graph(e, t_final);
             if (rc != VLBM_OK)
                 return rc;
         }
-        e->n_launch++;
+        while (left >= GRAPH_STEPS) {
+            HIP_TRY(hipGraphLaunch(e->graph, e->stream));
+            e->n_launch += GRAPH_STEPS;
+            left -= GRAPH_STEPS;
+        }
+    }
+    {
+        vlbm_status rc = eager(left);
+        if (rc != VLBM_OK)
+            return rc;
     }
     if (all_done) {
         std::vector<double> t, a;
@@ -636,13 +737,17 @@ vlbm_status vlbm_tune(vlbm_ensemble *e, int32_t kernel, int32_t chunk_rows)
 {
     if (!e)
         return fail(VLBM_ERR_ARG, "ensemble is NULL");
+    const bool no_graph = (kernel & VLBM_KERNEL_NO_GRAPH) != 0;
+    kernel &= ~VLBM_KERNEL_NO_GRAPH;
     if (kernel != VLBM_KERNEL_REFERENCE && kernel != VLBM_KERNEL_MARCH)
         return fail(VLBM_ERR_ARG, "unknown kernel %d", kernel);
     if (chunk_rows != 0 && (chunk_rows < 4 || chunk_rows > 65536))
         return fail(VLBM_ERR_ARG, "chunk_rows must be 0 or lie in [4, 65536] (got %d)", chunk_rows);
     e->kernel = kernel;
     e->chunk_rows = chunk_rows;
+    e->use_graph = !no_graph;
     std::fill(e->level_chunk.begin(), e->level_chunk.end(), 0);
+    drop_graph(e);
     return VLBM_OK;
 }
 
@@ -661,6 +766,7 @@ vlbm_status vlbm_autotune(vlbm_ensemble *e, double t_final, int32_t steps_per_ca
                 chunks_out[l] = 0;
         return VLBM_OK;
     }
+    drop_graph(e);
     // Candidates per level, ranked by the work model.
     const int max_cand = 6;
     std::vector<std::vector<int>> cand(nlev);
@@ -708,7 +814,7 @@ vlbm_status vlbm_autotune(vlbm_ensemble *e, double t_final, int32_t steps_per_ca
                 if (hipEventRecord(ev[l], e->stream) != hipSuccess)
                     rc = fail(VLBM_ERR_HIP, "hipEventRecord failed");
                 else
-                    rc = launch_step(e, ph, l, phase, t_final);
+                    rc = launch_step(e, ph, l, l + 1, phase, t_final, e->stream);
             }
             if (rc != VLBM_OK)
                 break;
@@ -762,6 +868,9 @@ vlbm_status vlbm_destroy(vlbm_ensemble *e)
     if (!e)
         return VLBM_OK;
     (void)hipStreamSynchronize(e->stream);
+    drop_graph(e);
+    if (e->cap_stream)
+        (void)hipStreamDestroy(e->cap_stream);
     if (e->ctl_mem)
         (void)hipFree(e->ctl_mem);
     if (e->coeffs_dev)

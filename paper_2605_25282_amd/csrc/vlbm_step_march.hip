@@ -37,9 +37,19 @@ struct MarchArgs {
     int nstrip;      // column strips per realization
     int chunk;       // rows per work item
     int nchunk;      // row chunks per realization
-    int nblocks;     // logical blocks (4 waves each); waves loop over the work items
-    int per_xcd;     // logical blocks per XCD slot
     int lane62_last; // 1: lane 62 of the last strip writes the copy column nx-1
+};
+
+// All mesh levels advanced by one launch: work items are concatenated level by
+// level (realization, row chunk, strip within a level).
+static constexpr int MAX_LEVELS = 8;
+struct MultiLevel {
+    int nlev;
+    int nblocks;                   // logical blocks (4 waves each) of the grid
+    int per_xcd;                   // logical blocks per XCD slot
+    long long item_off[MAX_LEVELS + 1];
+    LevelArgs L[MAX_LEVELS];
+    MarchArgs ma[MAX_LEVELS];
 };
 
 static constexpr int STRIP = 60;
@@ -72,21 +82,10 @@ __device__ __forceinline__ int from_left_i(int x) { return dpp_left_i(x); }
 __device__ __forceinline__ int from_right_i(int x) { return dpp_right_i(x); }
 
 template <int PREC>
-__global__ void __launch_bounds__(256, VLBM_MARCH_MIN_BLOCKS)
-step_march_kernel(PhysArgs ph, LevelArgs L, Ctl ctl, int phase, double t_final, MarchArgs ma)
+__device__ __forceinline__ void march_item(const PhysArgs &ph, const LevelArgs &L, const MarchArgs &ma,
+                                           const Ctl &ctl, int phase, double t_final, long long item, int lane)
 {
-    const int b = blockIdx.x;
-    const int lb = (b & 7) * ma.per_xcd + (b >> 3);
-    if (lb >= ma.nblocks)
-        return;
-    const int lane = threadIdx.x & 63;
     const long long per_real = (long long)ma.nstrip * ma.nchunk;
-    const long long n_items = per_real * L.R;
-    const long long grid_waves = (long long)ma.nblocks * 4;
-    // the wave index is uniform across the wave: keep it (and everything derived
-    // from it: work item, realization, plane bases, time control) in scalar registers
-    const int wid = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-    for (long long item = (long long)lb * 4 + wid; item < n_items; item += grid_waves) {
     const int m = (int)(item / per_real);
     const int rem = (int)(item % per_real);
     const int chunk = rem / ma.nstrip, strip = rem % ma.nstrip;
@@ -107,7 +106,7 @@ step_march_kernel(PhysArgs ph, LevelArgs L, Ctl ctl, int phase, double t_final, 
             ctl.amax[r1 * nr + cm] = ctl.amax[r0 * nr + cm];
             ctl.amax[r2 * nr + cm] = 0ull;
         }
-        continue;
+        return;
     }
     if (lead) {
         ctl.t[r1 * nr + cm] = sc.t_new;
@@ -427,10 +426,31 @@ step_march_kernel(PhysArgs ph, LevelArgs L, Ctl ctl, int phase, double t_final, 
         if (bad)
             atomicOr(&ctl.status[cm], bad & STATUS_NONFINITE ? STATUS_NONFINITE : STATUS_NONPOSITIVE);
     }
-    } // work items
 }
 
-template __global__ void step_march_kernel<0>(PhysArgs, LevelArgs, Ctl, int, double, MarchArgs);
-template __global__ void step_march_kernel<1>(PhysArgs, LevelArgs, Ctl, int, double, MarchArgs);
+template <int PREC>
+__global__ void __launch_bounds__(256, VLBM_MARCH_MIN_BLOCKS)
+step_march_kernel(PhysArgs ph, MultiLevel ml, Ctl ctl, int phase, double t_final)
+{
+    const int b = blockIdx.x;
+    const int lb = (b & 7) * ml.per_xcd + (b >> 3);
+    if (lb >= ml.nblocks)
+        return;
+    const int lane = threadIdx.x & 63;
+    const long long n_items = ml.item_off[ml.nlev];
+    const long long grid_waves = (long long)ml.nblocks * 4;
+    // the wave index is uniform across the wave: keep it (and everything derived
+    // from it: work item, realization, plane bases, time control) in scalar registers
+    const int wid = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    int l = 0;
+    for (long long item = (long long)lb * 4 + wid; item < n_items; item += grid_waves) {
+        while (item >= ml.item_off[l + 1])
+            ++l;
+        march_item<PREC>(ph, ml.L[l], ml.ma[l], ctl, phase, t_final, item - ml.item_off[l], lane);
+    }
+}
+
+template __global__ void step_march_kernel<0>(PhysArgs, MultiLevel, Ctl, int, double);
+template __global__ void step_march_kernel<1>(PhysArgs, MultiLevel, Ctl, int, double);
 
 } // namespace vlbm

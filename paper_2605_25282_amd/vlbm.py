@@ -195,7 +195,7 @@ def vlbm_w1(a, b, n_cells: int, m: int, w1_cell=None, w1_mean=None, stream=None)
                          _stream(stream)))
 
 
-KERNEL = {"reference": 0, "march": 1}
+KERNEL = {"reference": 0, "march": 1, "reference-eager": 0x100, "march-eager": 0x101}
 
 
 def vlbm_tune(h, kernel: str | int = "march", chunk_rows: int = 0) -> None:

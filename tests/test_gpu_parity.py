@@ -359,6 +359,81 @@ def test_autotune_is_result_neutral_and_cached():
         e.close()
 
 
+def _three_levels(nx0):
+    return [(nx0 << k, (nx0 << k) // 2, 1.0 / (nx0 << k), -0.25) for k in range(3)]
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_graph_replay_equals_eager(precision):
+    """Step runs long enough to be replayed from captured hipGraphs (a ragged lead to
+    re-align the control ring, whole 30-step graphs, an eager tail, repeated calls with
+    host reads in between) end bit-identical to eager launches of the marching and the
+    reference kernel, on three levels stepped by one launch per step."""
+    R = 5
+    levels = _three_levels(48)
+    coefs = inputs.kl_coefficients(inputs.DEFAULT_SEED, 7, R)
+    res = {}
+    for kern in ("march", "march-eager", "reference-eager"):
+        ens = vlbm.Ensemble(vlbm.Params.jet(precision=precision), levels, coefs, R)
+        ens.tune(kern, 0)
+        hist = []
+        for n in (1, 64, 33, 95):
+            ens.step(1e30, n)
+            hist.append(ens.times(1))
+        res[kern] = ([ens.state(l).cpu().numpy() for l in range(3)], hist)
+        ens.close()
+    for kern in ("march-eager", "reference-eager"):
+        for l in range(3):
+            assert np.array_equal(res["march"][0][l], res[kern][0][l]), (kern, l)
+        for ha, hb in zip(res["march"][1], res[kern][1]):
+            for a, b in zip(ha, hb):
+                assert np.array_equal(a, b)
+    assert np.all(res["march"][1][-1][1] == 193)
+
+
+def test_graph_replays_past_t_final():
+    """Replays that run past t_final leave finished realizations untouched: the run
+    ends at the same step counts, times and states as an eager run to t_final."""
+    R = 4
+    levels = _three_levels(32)
+    coefs = inputs.kl_coefficients(inputs.DEFAULT_SEED, 50, R)
+    t_final = 4e-4  # 24, 51 and 124 steps on the three levels
+    out = {}
+    for kern in ("march", "march-eager"):
+        ens = vlbm.Ensemble(vlbm.Params.jet(), levels, coefs, R)
+        ens.tune(kern, 0)
+        done = ens.step(t_final, 600)
+        assert done
+        out[kern] = [(ens.state(l).cpu().numpy(), ens.times(l)) for l in range(3)]
+        ens.close()
+    for l in range(3):
+        assert np.array_equal(out["march"][l][0], out["march-eager"][l][0])
+        for a, b in zip(out["march"][l][1], out["march-eager"][l][1]):
+            assert np.array_equal(a, b)
+        assert np.all(out["march"][l][1][0] == t_final)
+
+
+def test_multilevel_single_launch_matches_oracle():
+    """Three nested levels (48 x 24, 96 x 48, 192 x 96) advanced together, one launch
+    per step and graph replays, each against the oracle run of that level alone."""
+    R, steps = 3, 40
+    levels = _three_levels(48)
+    coefs = inputs.kl_coefficients(inputs.DEFAULT_SEED, 0, R)
+    ens = vlbm.Ensemble(vlbm.Params.jet(), levels, coefs, R)
+    ens.step(1e30, steps)
+    got = [(ens.state(l).cpu().numpy(), ens.times(l)) for l in range(3)]
+    ens.close()
+    p = O.Params()
+    for l, (nx, ny, dx, y_min) in enumerate(levels):
+        g = O.Grid(nx, ny, dx, y_min)
+        st, (t, s, a, status) = got[l]
+        assert np.all(s == steps) and np.all(status == 0)
+        for m in range(R):
+            r_st, r_t, r_n, r_a, rc = O.run(p, g, O.init(p, g, coefs[m]), 1e30, max_steps=steps)
+            assert rc == O.OK and r_n == steps and t[m] == r_t and a[m] == r_a
+            assert _plane_err(_to_oracle(st, m), r_st) <= TOL, (l, m)
+
+
 @pytest.mark.parametrize("alpha", [0.0, 1.0 / 3.0])
 def test_mixed_precision_matches_mixed_oracle(alpha):
     """Mixed storage (populations' rho, rho v in FP32; u and E populations FP64;
