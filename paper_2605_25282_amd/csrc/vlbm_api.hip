@@ -123,7 +123,7 @@ vlbm_status check_params(const vlbm_params *p)
     return VLBM_OK;
 }
 
-vlbm_status check_grid(int nx, int ny, int R)
+vlbm_status check_grid(int precision, int nx, int ny, int R)
 {
     if (nx < 3 || ny < 3)
         return fail(VLBM_ERR_SIZE, "a level needs nx, ny >= 3 (got %d x %d)", nx, ny);
@@ -131,6 +131,10 @@ vlbm_status check_grid(int nx, int ny, int R)
         return fail(VLBM_ERR_SIZE, "n_real must lie in [1, 65535] (got %d)", R);
     if ((ny + 3) / 4 > 65535)
         return fail(VLBM_ERR_SIZE, "ny = %d exceeds the launch grid", ny);
+    // kernels address a realization's state with 32-bit byte offsets
+    const double per_real = (double)nx * (double)ny * (precision == VLBM_FP64 ? 160.0 : 112.0);
+    if (per_real >= 4294967296.0)
+        return fail(VLBM_ERR_SIZE, "one realization of a %d x %d level needs %.0f bytes (limit 4 GiB)", nx, ny, per_real);
     if ((double)nx * (double)ny * (double)R * 20.0 > 9.0e15)
         return fail(VLBM_ERR_SIZE, "level too large");
     return VLBM_OK;
@@ -312,7 +316,7 @@ vlbm_status vlbm_state_bytes(const vlbm_params *p, int32_t nx, int32_t ny, int32
     vlbm_status rc = check_params(p);
     if (rc != VLBM_OK)
         return rc;
-    if ((rc = check_grid(nx, ny, n_real)) != VLBM_OK)
+    if ((rc = check_grid(p->precision, nx, ny, n_real)) != VLBM_OK)
         return rc;
     if (!bytes)
         return fail(VLBM_ERR_ARG, "bytes is NULL");
@@ -336,7 +340,7 @@ vlbm_status vlbm_init_ensemble(const vlbm_params *p, const vlbm_level *levels, i
         return fail(VLBM_ERR_ARG, "coeffs is NULL for the jet problem");
     for (int l = 0; l < n_levels; ++l) {
         const vlbm_level &L = levels[l];
-        if ((rc = check_grid(L.nx, L.ny, n_real)) != VLBM_OK)
+        if ((rc = check_grid(p->precision, L.nx, L.ny, n_real)) != VLBM_OK)
             return rc;
         if (!(L.dx > 0.0) || !std::isfinite(L.dx) || !std::isfinite(L.y_min))
             return fail(VLBM_ERR_ARG, "level %d: dx must be finite and > 0", l);

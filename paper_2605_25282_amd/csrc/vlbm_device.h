@@ -308,27 +308,39 @@ __device__ __forceinline__ StepCtl step_control(double t, double amax, double ka
 // State access.  FP64: double [4 var][5 slot][R][ny][nx].  Mixed: the var 0..2
 // planes as float (same index), padded to 256 B, then the var 3 planes as double.
 // ---------------------------------------------------------------------------
+// State layout of one level buffer, both precisions: realization-major, then
+// row-major, and within a row one contiguous block of `pitch` bytes holding the
+// rows of all 20 planes (v, s) of that mesh row.  A wave marching over the rows
+// of one realization therefore touches two compact address windows per row
+// (input and output buffer) instead of 40 planes far apart, and all of a
+// realization's state lies within 4 GiB of its first byte, so kernels address
+// it with one 64-bit base and 32-bit offsets.
+//   FP64:  plane (v, s) at byte (v * 5 + s) * nx * 8 of the row block,
+//          pitch = 160 * nx.
+//   mixed: FP64 rows first (u, 4 variables, then E of slots 1..4), then the
+//          FP32 rows of rho, rho v1, rho v2 of slots 1..4; pitch = 112 * nx.
 struct StateFP64 {
-    typedef double elem;
-    double *p;
-    size_t plane; // ny * nx
-    int R;
-    __device__ __forceinline__ size_t idx(int v, int s, int m, size_t node) const
+    char *p;
+    int nx, ny;
+    unsigned pitch; // bytes per row block
+    static constexpr unsigned PITCH_PER_COLUMN = 160;
+    __device__ static __forceinline__ StateFP64 make(void *b, int nx, int ny)
     {
-        return ((size_t)(v * 5 + s) * (size_t)R + (size_t)m) * plane + node;
+        return StateFP64{(char *)b, nx, ny, PITCH_PER_COLUMN * (unsigned)nx};
     }
-    __device__ __forceinline__ double ld(int v, int s, int m, size_t node) const { return p[idx(v, s, m, node)]; }
-    __device__ __forceinline__ void st(int v, int s, int m, size_t node, double x) const { p[idx(v, s, m, node)] = x; }
-    // value a store of x in variable v reads back as
-    __device__ __forceinline__ double stored(int, double x) const { return x; }
-    // wave-uniform base of plane (v, s) of realization m; elements addressed by a
-    // 32-bit byte offset (node * element size)
-    __device__ __forceinline__ const char *plane_base(int v, int s, int m) const
-    {
-        return (const char *)(p + ((size_t)(v * 5 + s) * (size_t)R + (size_t)m) * plane);
-    }
-    __device__ __forceinline__ char *plane_w(int v, int s, int m) const { return (char *)plane_base(v, s, m); }
     __device__ static __forceinline__ unsigned esize(int, int) { return 8u; }
+    // byte offset of plane (v, s) within a row block
+    __device__ static __forceinline__ unsigned poff(int nx, int v, int s) { return (unsigned)(v * 5 + s) * (unsigned)nx * 8u; }
+    // first byte of realization m
+    __device__ __forceinline__ char *real_base(int m) const { return p + (size_t)m * (size_t)ny * pitch; }
+    __device__ __forceinline__ size_t at(int v, int s, int m, int j, int i) const
+    {
+        return ((size_t)m * (size_t)ny + (size_t)j) * pitch + poff(nx, v, s) + (size_t)i * 8u;
+    }
+    __device__ __forceinline__ double ld(int v, int s, int m, int j, int i) const { return *(const double *)(p + at(v, s, m, j, i)); }
+    __device__ __forceinline__ void st(int v, int s, int m, int j, int i, double x) const { *(double *)(p + at(v, s, m, j, i)) = x; }
+    // value a store of x in variable v reads back as
+    __device__ static __forceinline__ double stored(int, double x) { return x; }
     __device__ static __forceinline__ double ldp(const char *base, int, int, unsigned off)
     {
         return *(const double *)(base + off);
@@ -347,61 +359,64 @@ struct StateFP64 {
 };
 
 struct StateMixed {
-    // FP64 part: slot 0 (u, 4 variables) then the E planes of slots 1..4;
-    // FP32 part: rho, rho v1, rho v2 planes of the populations (slots 1..4).
-    typedef double elem;
-    double *pd;
-    float *pf;
-    size_t plane;
-    int R;
-    __device__ __forceinline__ bool is_f32(int v, int s) const { return s > 0 && v < 3; }
-    __device__ __forceinline__ size_t d_index(int v, int s) const { return s == 0 ? (size_t)v : (size_t)(3 + s); }
-    __device__ __forceinline__ size_t f_index(int v, int s) const { return (size_t)(v * 4 + (s - 1)); }
-    __device__ __forceinline__ double ld(int v, int s, int m, size_t node) const
+    char *p;
+    int nx, ny;
+    unsigned pitch;
+    static constexpr unsigned PITCH_PER_COLUMN = 112;
+    __device__ static __forceinline__ StateMixed make(void *b, int nx, int ny)
     {
-        if (is_f32(v, s))
-            return (double)pf[(f_index(v, s) * (size_t)R + (size_t)m) * plane + node];
-        return pd[(d_index(v, s) * (size_t)R + (size_t)m) * plane + node];
+        return StateMixed{(char *)b, nx, ny, PITCH_PER_COLUMN * (unsigned)nx};
     }
-    __device__ __forceinline__ void st(int v, int s, int m, size_t node, double x) const
+    __device__ static __forceinline__ bool is_f32(int v, int s) { return s > 0 && v < 3; }
+    __device__ static __forceinline__ unsigned esize(int v, int s) { return is_f32(v, s) ? 4u : 8u; }
+    __device__ static __forceinline__ unsigned poff(int nx, int v, int s)
     {
         if (is_f32(v, s))
-            pf[(f_index(v, s) * (size_t)R + (size_t)m) * plane + node] = (float)x;
+            return 64u * (unsigned)nx + (unsigned)(v * 4 + (s - 1)) * (unsigned)nx * 4u;
+        return (unsigned)(s == 0 ? v : 3 + s) * (unsigned)nx * 8u;
+    }
+    __device__ __forceinline__ char *real_base(int m) const { return p + (size_t)m * (size_t)ny * pitch; }
+    __device__ __forceinline__ size_t at(int v, int s, int m, int j, int i) const
+    {
+        return ((size_t)m * (size_t)ny + (size_t)j) * pitch + poff(nx, v, s) + (size_t)i * esize(v, s);
+    }
+    __device__ __forceinline__ double ld(int v, int s, int m, int j, int i) const
+    {
+        const char *q = p + at(v, s, m, j, i);
+        return is_f32(v, s) ? (double)*(const float *)q : *(const double *)q;
+    }
+    __device__ __forceinline__ void st(int v, int s, int m, int j, int i, double x) const
+    {
+        char *q = p + at(v, s, m, j, i);
+        if (is_f32(v, s))
+            *(float *)q = (float)x;
         else
-            pd[(d_index(v, s) * (size_t)R + (size_t)m) * plane + node] = x;
+            *(double *)q = x;
     }
     // the macroscopic slot is FP64, so a stored u reads back unchanged
-    __device__ __forceinline__ double stored(int, double x) const { return x; }
-    __device__ __forceinline__ const char *plane_base(int v, int s, int m) const
-    {
-        if (is_f32(v, s))
-            return (const char *)(pf + (f_index(v, s) * (size_t)R + (size_t)m) * plane);
-        return (const char *)(pd + (d_index(v, s) * (size_t)R + (size_t)m) * plane);
-    }
-    __device__ __forceinline__ char *plane_w(int v, int s, int m) const { return (char *)plane_base(v, s, m); }
-    __device__ static __forceinline__ unsigned esize(int v, int s) { return (s > 0 && v < 3) ? 4u : 8u; }
+    __device__ static __forceinline__ double stored(int, double x) { return x; }
     __device__ static __forceinline__ double ldp(const char *base, int v, int s, unsigned off)
     {
-        if (s > 0 && v < 3)
+        if (is_f32(v, s))
             return (double)*(const float *)(base + off);
         return *(const double *)(base + off);
     }
     __device__ static __forceinline__ void stp(char *base, int v, int s, unsigned off, double x)
     {
-        if (s > 0 && v < 3)
+        if (is_f32(v, s))
             *(float *)(base + off) = (float)x;
         else
             *(double *)(base + off) = x;
     }
     __device__ static __forceinline__ unsigned long long ldraw(const char *base, int v, int s, unsigned off)
     {
-        if (s > 0 && v < 3)
+        if (is_f32(v, s))
             return (unsigned long long)*(const unsigned int *)(base + off);
         return *(const unsigned long long *)(base + off);
     }
     __device__ static __forceinline__ double decode(int v, int s, unsigned long long r)
     {
-        if (s > 0 && v < 3)
+        if (is_f32(v, s))
             return (double)__uint_as_float((unsigned int)r);
         return __longlong_as_double((long long)r);
     }
@@ -428,15 +443,11 @@ enum { LIM_RLMP = 0, LIM_ZERO = 1, LIM_ONE = 2 };
 template <int PREC> struct StateOf;
 template <> struct StateOf<0> {
     typedef StateFP64 type;
-    __device__ static type make(void *b, size_t plane, int R) { return StateFP64{(double *)b, plane, R}; }
+    __device__ static type make(void *b, int nx, int ny) { return StateFP64::make(b, nx, ny); }
 };
 template <> struct StateOf<1> {
     typedef StateMixed type;
-    __device__ static type make(void *b, size_t plane, int R)
-    {
-        const size_t dbytes = (size_t)8 * (size_t)R * plane * sizeof(double);
-        return StateMixed{(double *)b, (float *)((char *)b + dbytes), plane, R};
-    }
+    __device__ static type make(void *b, int nx, int ny) { return StateMixed::make(b, nx, ny); }
 };
 
 // Node kinds of reading R8: 0 interior, 1 Dirichlet inlet layer, 2 copy layer.

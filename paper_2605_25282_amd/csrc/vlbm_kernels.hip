@@ -20,7 +20,7 @@ __global__ void __launch_bounds__(256) init_macro_kernel(PhysArgs ph, LevelArgs 
     const int j = blockIdx.y * 4 + (threadIdx.x >> 6);
     const int m = blockIdx.z;
     const size_t plane = (size_t)L.nx * L.ny;
-    auto S = StateOf<PREC>::make(L.buf[0], plane, L.R);
+    auto S = StateOf<PREC>::make(L.buf[0], L.nx, L.ny);
     double s = 0.0;
     if (i < L.nx && j < L.ny) {
         double u[4];
@@ -57,10 +57,9 @@ __global__ void __launch_bounds__(256) init_macro_kernel(PhysArgs ph, LevelArgs 
             u[2] = 0.0;
             u[3] = ph.p_amb / (ph.gamma - 1.0);
         }
-        const size_t node = (size_t)j * L.nx + i;
 #pragma unroll
         for (int v = 0; v < 4; ++v)
-            S.st(v, 0, m, node, u[v]);
+            S.st(v, 0, m, j, i, u[v]);
         int bad = 0;
         s = wave_speed(ph.gamma, u, &bad);
         if (bad)
@@ -80,21 +79,20 @@ __global__ void __launch_bounds__(256) equilibrium_kernel(PhysArgs ph, LevelArgs
     if (i >= L.nx || j >= L.ny)
         return;
     const size_t plane = (size_t)L.nx * L.ny;
-    auto S = StateOf<PREC>::make(L.buf[buf], plane, L.R);
+    auto S = StateOf<PREC>::make(L.buf[buf], L.nx, L.ny);
     const double amax = __longlong_as_double((long long)ctl.amax[L.ctl_off + m]);
     const double a = ph.kappa * 2.0 * amax / (1.0 - ph.alpha);
     Phys P{ph.gamma, ph.alpha, (1.0 - ph.alpha) / 4.0, 1.0 / (2.0 * a), ph.rlmp_relax, ph.pos_eps};
-    const size_t node = (size_t)j * L.nx + i;
     double u[4], M[4][4];
 #pragma unroll
     for (int v = 0; v < 4; ++v)
-        u[v] = S.ld(v, 0, m, node);
+        u[v] = S.ld(v, 0, m, j, i);
     maxwellians(P, u, M);
 #pragma unroll
     for (int k = 0; k < 4; ++k)
 #pragma unroll
         for (int v = 0; v < 4; ++v)
-            S.st(v, 1 + k, m, node, M[k][v]);
+            S.st(v, 1 + k, m, j, i, M[k][v]);
 }
 
 // ---------------------------------------------------------------------------
@@ -105,22 +103,19 @@ template <class St>
 struct NodeAccess {
     St S;
     int m, nx, ny, bc;
-    __device__ __forceinline__ size_t node(int i, int j) const { return (size_t)j * nx + i; }
     __device__ __forceinline__ int wx(int i) const { return bc == BC_PERIODIC ? (i < 0 ? i + nx : (i >= nx ? i - nx : i)) : i; }
     __device__ __forceinline__ int wy(int j) const { return bc == BC_PERIODIC ? (j < 0 ? j + ny : (j >= ny ? j - ny : j)) : j; }
     __device__ __forceinline__ void load_u(int i, int j, double u[4]) const
     {
-        const size_t n = node(i, j);
 #pragma unroll
         for (int v = 0; v < 4; ++v)
-            u[v] = S.ld(v, 0, m, n);
+            u[v] = S.ld(v, 0, m, j, i);
     }
     __device__ __forceinline__ void load_pop(int k, int i, int j, double q[4]) const
     {
-        const size_t n = node(i, j);
 #pragma unroll
         for (int v = 0; v < 4; ++v)
-            q[v] = S.ld(v, 1 + k, m, n);
+            q[v] = S.ld(v, 1 + k, m, j, i);
     }
 };
 
@@ -287,8 +282,8 @@ __global__ void __launch_bounds__(256) step_ref_kernel(PhysArgs ph, LevelArgs L,
     }
     const Phys P{ph.gamma, ph.alpha, (1.0 - ph.alpha) / 4.0, 1.0 / (2.0 * sc.a), ph.rlmp_relax, ph.pos_eps};
     const size_t plane = (size_t)L.nx * L.ny;
-    auto Sin = StateOf<PREC>::make(L.buf[s & 1], plane, L.R);
-    auto Sout = StateOf<PREC>::make(L.buf[(s + 1) & 1], plane, L.R);
+    auto Sin = StateOf<PREC>::make(L.buf[s & 1], L.nx, L.ny);
+    auto Sout = StateOf<PREC>::make(L.buf[(s + 1) & 1], L.nx, L.ny);
     typedef typename StateOf<PREC>::type St;
     NodeAccess<St> A{Sin, m, L.nx, L.ny, ph.bc};
 
@@ -314,17 +309,16 @@ __global__ void __launch_bounds__(256) step_ref_kernel(PhysArgs ph, LevelArgs L,
             const int js = kind == 2 ? min(max(j, 1), L.ny - 2) : j;
             update_node(P, A, ph.limiter, is, js, out);
         }
-        const size_t n = (size_t)j * L.nx + i;
 #pragma unroll
         for (int sl = 0; sl < 5; ++sl)
 #pragma unroll
             for (int v = 0; v < 4; ++v)
-                Sout.st(v, sl, m, n, out[sl][v]);
+                Sout.st(v, sl, m, j, i, out[sl][v]);
         // Admissibility of the stored state and its wave speed (next a_n).
         double us[4];
 #pragma unroll
         for (int v = 0; v < 4; ++v)
-            us[v] = Sout.ld(v, 0, m, n);
+            us[v] = Sout.ld(v, 0, m, j, i);
         int bad = 0;
         wmax = wave_speed(ph.gamma, us, &bad);
         const bool finite = isfinite(us[0]) && isfinite(us[1]) && isfinite(us[2]) && isfinite(us[3]);
@@ -350,9 +344,9 @@ __global__ void __launch_bounds__(256) moments_kernel(PhysArgs ph, LevelArgs L, 
         return;
     const long long s = ctl.steps[phase * ctl.nr + L.ctl_off + m];
     const size_t plane = (size_t)L.nx * L.ny;
-    auto S = StateOf<PREC>::make(L.buf[s & 1], plane, L.R);
+    auto S = StateOf<PREC>::make(L.buf[s & 1], L.nx, L.ny);
     const size_t n = (size_t)j * L.nx + i;
-    const double rho = S.ld(0, 0, m, n), m1 = S.ld(1, 0, m, n), m2 = S.ld(2, 0, m, n), E = S.ld(3, 0, m, n);
+    const double rho = S.ld(0, 0, m, j, i), m1 = S.ld(1, 0, m, j, i), m2 = S.ld(2, 0, m, j, i), E = S.ld(3, 0, m, j, i);
     const double v1 = m1 / rho;
     const double v2 = m2 / rho;
     const size_t o = (size_t)m * plane + n;
@@ -374,11 +368,11 @@ __global__ void __launch_bounds__(256) get_state_kernel(LevelArgs L, Ctl ctl, in
         return;
     const long long s = ctl.steps[phase * ctl.nr + L.ctl_off + m];
     const size_t plane = (size_t)L.nx * L.ny;
-    auto S = StateOf<PREC>::make(L.buf[s & 1], plane, L.R);
+    auto S = StateOf<PREC>::make(L.buf[s & 1], L.nx, L.ny);
     const size_t n = (size_t)j * L.nx + i;
     for (int v = 0; v < 4; ++v)
         for (int sl = 0; sl < 5; ++sl)
-            out[((size_t)(v * 5 + sl) * L.R + m) * plane + n] = S.ld(v, sl, m, n);
+            out[((size_t)(v * 5 + sl) * L.R + m) * plane + n] = S.ld(v, sl, m, j, i);
 }
 
 // Load a macroscopic field [4][R][ny][nx] into slot 0 of buffer 0 and record
@@ -391,15 +385,15 @@ __global__ void __launch_bounds__(256) set_macro_kernel(PhysArgs ph, LevelArgs L
     const int j = blockIdx.y * 4 + (threadIdx.x >> 6);
     const int m = blockIdx.z;
     const size_t plane = (size_t)L.nx * L.ny;
-    auto S = StateOf<PREC>::make(L.buf[0], plane, L.R);
+    auto S = StateOf<PREC>::make(L.buf[0], L.nx, L.ny);
     double s = 0.0;
     if (i < L.nx && j < L.ny) {
         const size_t n = (size_t)j * L.nx + i;
         double u[4];
         for (int v = 0; v < 4; ++v) {
             u[v] = u_in[((size_t)v * L.R + m) * plane + n];
-            S.st(v, 0, m, n, u[v]);
-            u[v] = S.ld(v, 0, m, n);
+            S.st(v, 0, m, j, i, u[v]);
+            u[v] = S.ld(v, 0, m, j, i);
         }
         int bad = 0;
         s = wave_speed(ph.gamma, u, &bad);
@@ -437,13 +431,13 @@ __global__ void __launch_bounds__(256) stats_accumulate_kernel(PhysArgs ph, Leve
             mean[f] = sum[f] / (double)L.R;
         for (int m = 0; m < L.R; ++m) {
             const long long s = ctl.steps[phase * ctl.nr + L.ctl_off + m];
-            auto S = StateOf<PREC>::make(L.buf[s & 1], plane, L.R);
+            auto S = StateOf<PREC>::make(L.buf[s & 1], L.nx, L.ny);
             double blk[3] = {0.0, 0.0, 0.0};
             for (int dj = 0; dj < r; ++dj)
                 for (int di = 0; di < r; ++di) {
-                    const size_t n = (size_t)(cj * r + dj) * L.nx + (ci * r + di);
-                    const double rho = S.ld(0, 0, m, n), m1 = S.ld(1, 0, m, n), m2v = S.ld(2, 0, m, n),
-                                 E = S.ld(3, 0, m, n);
+                    const int jj = cj * r + dj, ii = ci * r + di;
+                    const double rho = S.ld(0, 0, m, jj, ii), m1 = S.ld(1, 0, m, jj, ii),
+                                 m2v = S.ld(2, 0, m, jj, ii), E = S.ld(3, 0, m, jj, ii);
                     const double v1 = m1 / rho, v2 = m2v / rho;
                     blk[0] += rho;
                     blk[1] += sqrt(v1 * v1 + v2 * v2);

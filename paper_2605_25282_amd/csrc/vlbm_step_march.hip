@@ -117,24 +117,17 @@ __device__ __forceinline__ void march_item(const PhysArgs &ph, const LevelArgs &
     const Phys P{ph.gamma, ph.alpha, (1.0 - ph.alpha) / 4.0, 1.0 / (2.0 * sc.a), ph.rlmp_relax, ph.pos_eps};
     const int nx = L.nx, ny = L.ny, bc = ph.bc, lim = ph.limiter;
     const bool periodic = bc == BC_PERIODIC;
-    const size_t plane = (size_t)nx * ny;
     typedef typename StateOf<PREC>::type St;
-    const St Sin = StateOf<PREC>::make(L.buf[s & 1], plane, L.R);
-    const St Sout = StateOf<PREC>::make(L.buf[(s + 1) & 1], plane, L.R);
-    // wave-uniform plane bases of the input buffer; the output buffer has the
-    // same layout, so its planes sit one uniform byte distance further on
-    const char *inU[4], *inP[4][4];
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-        inU[v] = Sin.plane_base(v, 0, m);
-#pragma unroll
-        for (int q = 0; q < 4; ++q)
-            inP[q][v] = Sin.plane_base(v, 1 + q, m);
-    }
-    const long long out_delta = (const char *)L.buf[(s + 1) & 1] - (const char *)L.buf[s & 1];
-    auto out_plane = [&](int sl, int v) -> char * {
-        return (char *)(sl == 0 ? inU[v] : inP[sl - 1][v]) + out_delta;
-    };
+    const St Sin = StateOf<PREC>::make(L.buf[s & 1], nx, ny);
+    const St Sout = StateOf<PREC>::make(L.buf[(s + 1) & 1], nx, ny);
+    // Wave-uniform base of this realization in the input and output buffers;
+    // a row of a plane sits at a 32-bit byte offset from it (a realization's
+    // state is below 4 GiB), so every access is one scalar base plus the
+    // lane's column offset.
+    const char *const inb = Sin.real_base(m);
+    char *const outb = Sout.real_base(m);
+    const unsigned pitch = Sin.pitch;
+    auto row_off = [&](int j, int v, int sl) -> size_t { return (size_t)((unsigned)j * pitch + St::poff(nx, v, sl)); };
 
     // ---- geometry of this lane ----
     const int c = strip * STRIP - 2 + lane; // column
@@ -161,15 +154,15 @@ __device__ __forceinline__ void march_item(const PhysArgs &ph, const LevelArgs &
             return true;
         return kind_col_interior && j >= 1 && j <= ny - 2;
     };
-    auto off_of = [&](int j, int col, int v, int sl) -> unsigned {
-        return (unsigned)((size_t)j * nx + col) * St::esize(v, sl);
-    };
+    // lane column offsets within a row (loads read the clamped column cx)
+    auto col_in = [&](int v, int sl) -> unsigned { return (unsigned)cx * St::esize(v, sl); };
+    auto col_out = [&](int v, int sl) -> unsigned { return (unsigned)c * St::esize(v, sl); };
     double wmax = 0.0;
     int bad = 0;
     auto store_slot = [&](int sl, int j, const double x[4]) {
 #pragma unroll
         for (int v = 0; v < 4; ++v)
-            St::stp(out_plane(sl, v), v, sl, off_of(j, c, v, sl), x[v]);
+            St::stp(outb + row_off(j, v, sl), v, sl, col_out(v, sl), x[v]);
     };
     auto account = [&](const double u[4]) {
         double us[4];
@@ -204,30 +197,51 @@ __device__ __forceinline__ void march_item(const PhysArgs &ph, const LevelArgs &
     // ---- register ring ----
     // Row k-2, finished in iteration k: (u1+u2)+u3, the correction without its
     // north-face term, N_3 and M_3, the low-order state and its bounds.
-    double U0[4], U1[4];
+    double U1[4];
     double pC[4], cC[4], N3C[4], M3C[4], LC[4], bC[3];
-    double Un[4];               // load in flight: U(k+1)
-    unsigned long long Pn[4][4]; // loads in flight: populations of row k (raw element bits)
+    // Prefetch ring, two rows deep: buffer X_k holds the macroscopic row k and the
+    // population row k-1 used by iteration k; it is refilled with X_{k+2} as soon
+    // as it has been read.  Loads are unconditional (rows clamped to the chunk's
+    // range; the surplus ones re-read rows just fetched), so at least the 20 loads
+    // of X_{k+1} are always issued after those of X_k and the wait for X_k never
+    // has to wait for the stores of the previous iteration.
+    double UA[4], UB[4];
+    unsigned long long PA[4][4], PB[4][4]; // raw element bits
 
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
         U1[v] = (v == 0 || v == 3) ? 1.0 : 0.0; // placeholder row before the first load
         pC[v] = cC[v] = N3C[v] = M3C[v] = LC[v] = 0.0;
-#pragma unroll
-        for (int q = 0; q < 4; ++q)
-            Pn[q][v] = 0ull;
     }
     bC[0] = bC[1] = bC[2] = 0.0;
 
     const int k_first = y0 - 2, k_last = y1 + 1;
-#pragma unroll
-    for (int v = 0; v < 4; ++v)
-        Un[v] = St::ldp(inU[v], v, 0, off_of(row_of(k_first), cx, v, 0));
-
-    for (int k = k_first; k <= k_last; ++k) {
+    // population row needed by iteration k is k-1; rows below y0-1 or above y1
+    // never reach a stored value
+    auto prow = [&](int k) { return row_of(min(max(k - 1, y0 - 1), y1)); };
+    auto urow = [&](int k) { return row_of(min(k, k_last)); };
+    auto load_x = [&](int k, double (&Ux)[4], unsigned long long (&Px)[4][4]) {
+        const int ju = urow(k), jp = prow(k);
 #pragma unroll
         for (int v = 0; v < 4; ++v)
-            U0[v] = Un[v];
+            Ux[v] = St::ldp(inb + row_off(ju, v, 0), v, 0, col_in(v, 0));
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int v = 0; v < 4; ++v)
+                Px[q][v] = St::ldraw(inb + row_off(jp, v, 1 + q), v, 1 + q, col_in(v, 1 + q));
+    };
+    // an even number of iterations (a leading one on rows that are never stored
+    // when chunk + 4 is odd), so the two buffers alternate without a join
+    const int k_start = k_first - ((k_last - k_first + 1) & 1);
+    load_x(k_start, UA, PA);
+    load_x(k_start + 1, UB, PB);
+
+    auto iteration = [&](int k, double (&Ux)[4], unsigned long long (&Px)[4][4]) __attribute__((always_inline)) {
+        double U0[4];
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+            U0[v] = Ux[v];
         // Row k-1: Maxwellians and non-equilibrium parts (its populations arrived).
         double MB[4][4], NB[4][4];
         maxwellians(P, U1, MB);
@@ -235,22 +249,8 @@ __device__ __forceinline__ void march_item(const PhysArgs &ph, const LevelArgs &
         for (int q = 0; q < 4; ++q)
 #pragma unroll
             for (int v = 0; v < 4; ++v)
-                NB[q][v] = MB[q][v] - St::decode(v, 1 + q, Pn[q][v]);
-        // Issue the next loads: macroscopic row k+1 and population row k.
-        if (k < k_last) {
-            const int jr = row_of(k + 1);
-#pragma unroll
-            for (int v = 0; v < 4; ++v)
-                Un[v] = St::ldp(inU[v], v, 0, off_of(jr, cx, v, 0));
-        }
-        if (k >= y0 - 1 && k <= y1) { // population row k is row k-1 of the next iteration
-            const int jr = row_of(k);
-#pragma unroll
-            for (int q = 0; q < 4; ++q)
-#pragma unroll
-                for (int v = 0; v < 4; ++v)
-                    Pn[q][v] = St::ldraw(inP[q][v], v, 1 + q, off_of(jr, cx, v, 1 + q));
-        }
+                NB[q][v] = MB[q][v] - St::decode(v, 1 + q, Px[q][v]);
+        load_x(k + 2, Ux, Px);
 
         // Low-order state and bounds of row k-1.
         const int jB = k - 1;
@@ -413,6 +413,11 @@ __device__ __forceinline__ void march_item(const PhysArgs &ph, const LevelArgs &
         bC[0] = bB[0];
         bC[1] = bB[1];
         bC[2] = bB[2];
+    };
+
+    for (int k = k_start; k <= k_last; k += 2) {
+        iteration(k, UA, PA);
+        iteration(k + 1, UB, PB);
     }
 
     // ---- wave-speed maximum (next a_n) and latched status ----

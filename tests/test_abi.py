@@ -54,6 +54,18 @@ def test_invalid_sizes_rejected(lib, nx, ny, R):
     assert ei.value.code == vlbm.ERR_SIZE
 
 
+def test_realization_state_limit(lib):
+    """Kernels address one realization's state with 32-bit byte offsets: a level
+    whose realization needs 4 GiB or more is refused up front; the mixed layout
+    (112 B per node instead of 160) admits larger levels."""
+    with pytest.raises(vlbm.VlbmError) as ei:
+        vlbm.vlbm_state_bytes(vlbm.Params.jet(), 6000, 5000, 1)
+    assert ei.value.code == vlbm.ERR_SIZE and "4 GiB" in vlbm.last_error()
+    assert vlbm.vlbm_state_bytes(vlbm.Params.jet(precision="mixed"), 6000, 5000, 1) == 112 * 6000 * 5000
+    # the largest configuration of the study (5056 x 2528) fits in FP64
+    assert vlbm.vlbm_state_bytes(vlbm.Params.jet(), 5056, 2528, 2) == 2 * 160 * 5056 * 2528
+
+
 def test_init_rejects_before_any_device_work(lib):
     """Validation happens before any HIP call, so these run without a GPU."""
     p = vlbm.Params.jet()
