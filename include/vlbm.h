@@ -33,22 +33,26 @@
  *
  * State layout of one mesh level, in one state buffer: realization-major,
  * then row-major, each mesh row one contiguous block holding that row of all
- * 20 planes (var, slot):
- *     FP64:  double st[R realizations][ny][4 var][5 slot][nx]   (160 B per node)
+ * 20 planes (var, slot); a plane row is W = 64 * nstrip elements wide, the
+ * columns grouped in strips of 60 (column i in element slot 64 q + i - 60 q,
+ * q = min(i / 60, nstrip - 1)), nstrip = ceil(nx / 60), or (nx - 1) / 60 for a
+ * non-periodic level with (nx - 1) divisible by 60:
+ *     FP64:  double st[R realizations][ny][4 var][5 slot][W]   (160 B per slot)
  * var = (rho, rho v1, rho v2, E); slot 0 is the macroscopic state u, slots
  * 1..4 are the populations u_1..u_4 (u_5 is eliminated, Sec. 2.1).  Node
- * (i, j) sits at x = (i + 1/2) dx, y = y_min + (j + 1/2) dx.  Two buffers of
- * vlbm_state_bytes() each are needed per level; which one holds a given
- * realization's current state depends on its step count, so read states only
- * through vlbm_get_state, vlbm_moments or vlbm_ensemble_stats.
+ * (i, j) sits at x = (i + 1/2) dx, y = y_min + (j + 1/2) dx.  The unused slots
+ * hold no data.  Two buffers of vlbm_state_bytes() each are needed per level;
+ * which one holds a given realization's current state depends on its step
+ * count, so read states only through vlbm_get_state, vlbm_moments or
+ * vlbm_ensemble_stats.
  * With VLBM_MIXED the populations' rho, rho v1, rho v2 are stored in FP32 and
  * everything else in FP64; the row block of (realization, row) holds
- * double u[4 var][nx], double E_k[4 slot][nx], then float q[3 var][4 slot][nx]
- * (112 B per node).  All arithmetic, the pressure recovery and the
+ * double u[4 var][W], double E_k[4 slot][W], then float q[3 var][4 slot][W]
+ * (112 B per slot).  All arithmetic, the pressure recovery and the
  * admissibility check are FP64.
- * One realization's state must stay below 4 GiB (nx * ny < 26.8 M nodes in
- * FP64, 38.3 M in mixed precision); larger levels are rejected with
- * VLBM_ERR_SIZE.
+ * One realization's state must stay below 4 GiB (about 24.9 M nodes in FP64,
+ * 35.5 M in mixed precision, for nx a multiple of 60); larger levels are
+ * rejected with VLBM_ERR_SIZE.
  */
 #ifndef VLBM_H
 #define VLBM_H

@@ -80,14 +80,13 @@ vlbm_status fail(vlbm_status code, const char *fmt, ...)
             return fail(VLBM_ERR_HIP, "%s launch failed: %s", what, hipGetErrorString(e_)); \
     } while (0)
 
-size_t state_bytes(int prec, int nx, int ny, int R)
+// Bytes of one state buffer: R x ny row blocks of 20 plane rows, each plane row
+// 64 element slots per column strip (FP64: 160 B per slot; mixed: 8 FP64 and
+// 12 FP32 planes, 112 B per slot).
+size_t state_bytes(int prec, int bc, int nx, int ny, int R)
 {
-    const size_t plane = (size_t)nx * (size_t)ny;
-    if (prec == VLBM_FP64)
-        return (size_t)20 * (size_t)R * plane * sizeof(double);
-    // FP64: u (4 planes) and the E populations (4 planes); FP32: rho, rho v1, rho v2
-    // populations (12 planes) -- 112 B per node
-    return (size_t)8 * (size_t)R * plane * sizeof(double) + (size_t)12 * (size_t)R * plane * sizeof(float);
+    const size_t slots = (size_t)SLOTS * (size_t)strip_count(nx, bc == VLBM_BC_PERIODIC);
+    return (size_t)R * (size_t)ny * slots * (prec == VLBM_FP64 ? 160u : 112u);
 }
 
 vlbm_status check_params(const vlbm_params *p)
@@ -123,7 +122,7 @@ vlbm_status check_params(const vlbm_params *p)
     return VLBM_OK;
 }
 
-vlbm_status check_grid(int precision, int nx, int ny, int R)
+vlbm_status check_grid(int precision, int bc, int nx, int ny, int R)
 {
     if (nx < 3 || ny < 3)
         return fail(VLBM_ERR_SIZE, "a level needs nx, ny >= 3 (got %d x %d)", nx, ny);
@@ -132,7 +131,7 @@ vlbm_status check_grid(int precision, int nx, int ny, int R)
     if ((ny + 3) / 4 > 65535)
         return fail(VLBM_ERR_SIZE, "ny = %d exceeds the launch grid", ny);
     // kernels address a realization's state with 32-bit byte offsets
-    const double per_real = (double)nx * (double)ny * (precision == VLBM_FP64 ? 160.0 : 112.0);
+    const double per_real = (double)state_bytes(precision, bc, nx, ny, 1);
     if (per_real >= 4294967296.0)
         return fail(VLBM_ERR_SIZE, "one realization of a %d x %d level needs %.0f bytes (limit 4 GiB)", nx, ny, per_real);
     if ((double)nx * (double)ny * (double)R * 20.0 > 9.0e15)
@@ -191,15 +190,13 @@ namespace {
 int phase_of(const vlbm_ensemble *e) { return (int)(e->n_launch % 3); }
 
 // Work decomposition of the marching kernel for one level.
+// Strips of the marching kernel = column strips of the state layout; lane 62 of
+// the last strip carries the last column of a bounded level of 60 q + 1 columns.
 int strips_of(const vlbm_ensemble *e, const LevelArgs &L, int *lane62)
 {
     const bool periodic = e->p.bc == VLBM_BC_PERIODIC;
-    if (!periodic && (L.nx - 1) % 60 == 0) {
-        *lane62 = 1;
-        return (L.nx - 1) / 60;
-    }
-    *lane62 = 0;
-    return (L.nx + 59) / 60;
+    *lane62 = (!periodic && (L.nx - 1) % STRIP == 0) ? 1 : 0;
+    return L.nstrip;
 }
 
 // Default chunk height: about twelve work items per resident wave, rows >= 16.
@@ -316,11 +313,11 @@ vlbm_status vlbm_state_bytes(const vlbm_params *p, int32_t nx, int32_t ny, int32
     vlbm_status rc = check_params(p);
     if (rc != VLBM_OK)
         return rc;
-    if ((rc = check_grid(p->precision, nx, ny, n_real)) != VLBM_OK)
+    if ((rc = check_grid(p->precision, p->bc, nx, ny, n_real)) != VLBM_OK)
         return rc;
     if (!bytes)
         return fail(VLBM_ERR_ARG, "bytes is NULL");
-    *bytes = state_bytes(p->precision, nx, ny, n_real);
+    *bytes = state_bytes(p->precision, p->bc, nx, ny, n_real);
     return VLBM_OK;
 }
 
@@ -340,7 +337,7 @@ vlbm_status vlbm_init_ensemble(const vlbm_params *p, const vlbm_level *levels, i
         return fail(VLBM_ERR_ARG, "coeffs is NULL for the jet problem");
     for (int l = 0; l < n_levels; ++l) {
         const vlbm_level &L = levels[l];
-        if ((rc = check_grid(p->precision, L.nx, L.ny, n_real)) != VLBM_OK)
+        if ((rc = check_grid(p->precision, p->bc, L.nx, L.ny, n_real)) != VLBM_OK)
             return rc;
         if (!(L.dx > 0.0) || !std::isfinite(L.dx) || !std::isfinite(L.y_min))
             return fail(VLBM_ERR_ARG, "level %d: dx must be finite and > 0", l);
@@ -361,8 +358,8 @@ vlbm_status vlbm_init_ensemble(const vlbm_params *p, const vlbm_level *levels, i
     e->stream = (hipStream_t)hip_stream;
     const int nr = n_real * n_levels;
     for (int l = 0; l < n_levels; ++l) {
-        LevelArgs L{levels[l].nx, levels[l].ny, n_real, l * n_real, levels[l].dx, levels[l].y_min,
-                    {levels[l].state[0], levels[l].state[1]}};
+        LevelArgs L{levels[l].nx, levels[l].ny, n_real, strip_count(levels[l].nx, p->bc == VLBM_BC_PERIODIC),
+                    l * n_real, levels[l].dx, levels[l].y_min, {levels[l].state[0], levels[l].state[1]}};
         e->levels.push_back(L);
     }
     const size_t ctl_bytes = (size_t)3 * nr * (sizeof(double) * 2 + sizeof(long long) + sizeof(unsigned long long)) +

@@ -25,6 +25,8 @@ struct Phys {
     double h;          // 1 / (2 a), a = kinetic speed of the step
     double rlmp_relax; // relaxation of the local density bounds
     double pos_eps;    // internal-energy floor (fraction of the low-order value)
+    double inv_w;      // 1 / w
+    bool w_pow2;       // w is a power of two: x / w == x * inv_w exactly
 };
 
 // ---------------------------------------------------------------------------
@@ -76,8 +78,18 @@ __device__ __forceinline__ void cell_bounds(const Phys &P, const double L[4], do
 {
     // Division by w > 0 is monotone, so the largest (smallest) bar density
     // max_k M_k/w equals (max_k M_k)/w bit for bit: two divisions, not four.
-    double rmax = fmax(fmax(m1w_rho, m2e_rho), fmax(m3s_rho, m4n_rho)) / P.w;
-    double rmin = fmin(fmin(m1w_rho, m2e_rho), fmin(m3s_rho, m4n_rho)) / P.w;
+    // When w is a power of two (alpha = 0: w = 1/4) the division is an exact
+    // scaling and the product with 1/w is the same number.
+    const double mx = fmax(fmax(m1w_rho, m2e_rho), fmax(m3s_rho, m4n_rho));
+    const double mn = fmin(fmin(m1w_rho, m2e_rho), fmin(m3s_rho, m4n_rho));
+    double rmax, rmin;
+    if (P.w_pow2) {
+        rmax = mx * P.inv_w;
+        rmin = mn * P.inv_w;
+    } else {
+        rmax = mx / P.w;
+        rmin = mn / P.w;
+    }
     if (P.alpha > 0.0) {
         rmax = fmax(rmax, rho_c);
         rmin = fmin(rmin, rho_c);
@@ -315,27 +327,52 @@ __device__ __forceinline__ StepCtl step_control(double t, double amax, double ka
 // (input and output buffer) instead of 40 planes far apart, and all of a
 // realization's state lies within 4 GiB of its first byte, so kernels address
 // it with one 64-bit base and 32-bit offsets.
-//   FP64:  plane (v, s) at byte (v * 5 + s) * nx * 8 of the row block,
-//          pitch = 160 * nx.
+// Within a plane row the columns are grouped by the step kernel's strips: strip
+// q (columns 60q .. 60q+59, the last strip also column 60q+60 when that is the
+// last column of a bounded level) occupies the 64 element slots 64q .. 64q+63,
+// so the wave of a strip writes whole 128-byte lines (the unused slots take
+// whatever its halo lanes hold); plane rows are 64 * nstrip elements wide.
+//   FP64:  plane (v, s) at element offset (v * 5 + s) * W of the row block,
+//          W = 64 * nstrip, pitch = 160 * W bytes.
 //   mixed: FP64 rows first (u, 4 variables, then E of slots 1..4), then the
-//          FP32 rows of rho, rho v1, rho v2 of slots 1..4; pitch = 112 * nx.
+//          FP32 rows of rho, rho v1, rho v2 of slots 1..4; pitch = 112 * W.
+static constexpr int STRIP = 60;   // output columns per strip
+static constexpr int SLOTS = 64;   // element slots per strip in a plane row
+
+// Strips per row: ceil(nx / 60), except that a bounded level whose last column
+// is 60 q + 60 lets the last strip's lane 62 carry it (that column is a copy of
+// its left neighbour, which the same wave computes).
+__host__ __device__ inline int strip_count(int nx, bool periodic)
+{
+    if (!periodic && (nx - 1) % STRIP == 0)
+        return (nx - 1) / STRIP;
+    return (nx + STRIP - 1) / STRIP;
+}
+
+// element slot of column i within a plane row
+__device__ __forceinline__ unsigned col_slot(int i, int nstrip)
+{
+    const int q = min(i / STRIP, nstrip - 1);
+    return (unsigned)(SLOTS * q + (i - STRIP * q));
+}
+
 struct StateFP64 {
     char *p;
-    int nx, ny;
-    unsigned pitch; // bytes per row block
-    static constexpr unsigned PITCH_PER_COLUMN = 160;
-    __device__ static __forceinline__ StateFP64 make(void *b, int nx, int ny)
+    int W, ny, nstrip; // W: elements per plane row (64 * nstrip)
+    unsigned pitch;    // bytes per row block
+    static constexpr unsigned PITCH_PER_SLOT = 160;
+    __device__ static __forceinline__ StateFP64 make(void *b, int ny, int nstrip)
     {
-        return StateFP64{(char *)b, nx, ny, PITCH_PER_COLUMN * (unsigned)nx};
+        return StateFP64{(char *)b, SLOTS * nstrip, ny, nstrip, PITCH_PER_SLOT * (unsigned)(SLOTS * nstrip)};
     }
     __device__ static __forceinline__ unsigned esize(int, int) { return 8u; }
-    // byte offset of plane (v, s) within a row block
-    __device__ static __forceinline__ unsigned poff(int nx, int v, int s) { return (unsigned)(v * 5 + s) * (unsigned)nx * 8u; }
+    // byte offset of plane (v, s) within a row block of plane rows W elements wide
+    __device__ static __forceinline__ unsigned poff(int W, int v, int s) { return (unsigned)(v * 5 + s) * (unsigned)W * 8u; }
     // first byte of realization m
     __device__ __forceinline__ char *real_base(int m) const { return p + (size_t)m * (size_t)ny * pitch; }
     __device__ __forceinline__ size_t at(int v, int s, int m, int j, int i) const
     {
-        return ((size_t)m * (size_t)ny + (size_t)j) * pitch + poff(nx, v, s) + (size_t)i * 8u;
+        return ((size_t)m * (size_t)ny + (size_t)j) * pitch + poff(W, v, s) + (size_t)col_slot(i, nstrip) * 8u;
     }
     __device__ __forceinline__ double ld(int v, int s, int m, int j, int i) const { return *(const double *)(p + at(v, s, m, j, i)); }
     __device__ __forceinline__ void st(int v, int s, int m, int j, int i, double x) const { *(double *)(p + at(v, s, m, j, i)) = x; }
@@ -345,9 +382,10 @@ struct StateFP64 {
     {
         return *(const double *)(base + off);
     }
+    // streaming store (the step kernel writes every line once, whole)
     __device__ static __forceinline__ void stp(char *base, int, int, unsigned off, double x)
     {
-        *(double *)(base + off) = x;
+        __builtin_nontemporal_store(x, (double *)(base + off));
     }
     // Raw element bits for prefetching: the conversion to double happens at the
     // point of use, so a load in flight is not waited for at the loop back-edge.
@@ -360,25 +398,25 @@ struct StateFP64 {
 
 struct StateMixed {
     char *p;
-    int nx, ny;
+    int W, ny, nstrip;
     unsigned pitch;
-    static constexpr unsigned PITCH_PER_COLUMN = 112;
-    __device__ static __forceinline__ StateMixed make(void *b, int nx, int ny)
+    static constexpr unsigned PITCH_PER_SLOT = 112;
+    __device__ static __forceinline__ StateMixed make(void *b, int ny, int nstrip)
     {
-        return StateMixed{(char *)b, nx, ny, PITCH_PER_COLUMN * (unsigned)nx};
+        return StateMixed{(char *)b, SLOTS * nstrip, ny, nstrip, PITCH_PER_SLOT * (unsigned)(SLOTS * nstrip)};
     }
     __device__ static __forceinline__ bool is_f32(int v, int s) { return s > 0 && v < 3; }
     __device__ static __forceinline__ unsigned esize(int v, int s) { return is_f32(v, s) ? 4u : 8u; }
-    __device__ static __forceinline__ unsigned poff(int nx, int v, int s)
+    __device__ static __forceinline__ unsigned poff(int W, int v, int s)
     {
         if (is_f32(v, s))
-            return 64u * (unsigned)nx + (unsigned)(v * 4 + (s - 1)) * (unsigned)nx * 4u;
-        return (unsigned)(s == 0 ? v : 3 + s) * (unsigned)nx * 8u;
+            return 64u * (unsigned)W + (unsigned)(v * 4 + (s - 1)) * (unsigned)W * 4u;
+        return (unsigned)(s == 0 ? v : 3 + s) * (unsigned)W * 8u;
     }
     __device__ __forceinline__ char *real_base(int m) const { return p + (size_t)m * (size_t)ny * pitch; }
     __device__ __forceinline__ size_t at(int v, int s, int m, int j, int i) const
     {
-        return ((size_t)m * (size_t)ny + (size_t)j) * pitch + poff(nx, v, s) + (size_t)i * esize(v, s);
+        return ((size_t)m * (size_t)ny + (size_t)j) * pitch + poff(W, v, s) + (size_t)col_slot(i, nstrip) * esize(v, s);
     }
     __device__ __forceinline__ double ld(int v, int s, int m, int j, int i) const
     {
@@ -401,12 +439,13 @@ struct StateMixed {
             return (double)*(const float *)(base + off);
         return *(const double *)(base + off);
     }
+    // streaming store (the step kernel writes every line once, whole)
     __device__ static __forceinline__ void stp(char *base, int v, int s, unsigned off, double x)
     {
         if (is_f32(v, s))
-            *(float *)(base + off) = (float)x;
+            __builtin_nontemporal_store((float)x, (float *)(base + off));
         else
-            *(double *)(base + off) = x;
+            __builtin_nontemporal_store(x, (double *)(base + off));
     }
     __device__ static __forceinline__ unsigned long long ldraw(const char *base, int v, int s, unsigned off)
     {
@@ -425,6 +464,7 @@ struct StateMixed {
 // Launch arguments of one mesh level and of the physics (plain values).
 struct LevelArgs {
     int nx, ny, R;   // nodes incl. layers, realizations
+    int nstrip;      // column strips of the state layout (strip_count)
     int ctl_off;     // index of realization 0 of this level in the control arrays
     double dx, y_min;
     void *buf[2];    // ping-pong state buffers
@@ -437,17 +477,33 @@ struct PhysArgs {
 };
 
 
+// Scheme parameters of one step of a realization whose kinetic speed is a.
+__device__ __forceinline__ Phys make_phys(const PhysArgs &ph, double a)
+{
+    Phys P;
+    P.gamma = ph.gamma;
+    P.alpha = ph.alpha;
+    P.w = (1.0 - ph.alpha) / 4.0;
+    P.h = 1.0 / (2.0 * a);
+    P.rlmp_relax = ph.rlmp_relax;
+    P.pos_eps = ph.pos_eps;
+    P.inv_w = 1.0 / P.w;
+    int e;
+    P.w_pow2 = frexp(P.w, &e) == 0.5;
+    return P;
+}
+
 enum { BC_JET = 0, BC_PERIODIC = 1, BC_NEUMANN = 2 };
 enum { LIM_RLMP = 0, LIM_ZERO = 1, LIM_ONE = 2 };
 
 template <int PREC> struct StateOf;
 template <> struct StateOf<0> {
     typedef StateFP64 type;
-    __device__ static type make(void *b, int nx, int ny) { return StateFP64::make(b, nx, ny); }
+    __device__ static type make(void *b, int ny, int nstrip) { return StateFP64::make(b, ny, nstrip); }
 };
 template <> struct StateOf<1> {
     typedef StateMixed type;
-    __device__ static type make(void *b, int nx, int ny) { return StateMixed::make(b, nx, ny); }
+    __device__ static type make(void *b, int ny, int nstrip) { return StateMixed::make(b, ny, nstrip); }
 };
 
 // Node kinds of reading R8: 0 interior, 1 Dirichlet inlet layer, 2 copy layer.

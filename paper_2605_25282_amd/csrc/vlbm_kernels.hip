@@ -20,7 +20,7 @@ __global__ void __launch_bounds__(256) init_macro_kernel(PhysArgs ph, LevelArgs 
     const int j = blockIdx.y * 4 + (threadIdx.x >> 6);
     const int m = blockIdx.z;
     const size_t plane = (size_t)L.nx * L.ny;
-    auto S = StateOf<PREC>::make(L.buf[0], L.nx, L.ny);
+    auto S = StateOf<PREC>::make(L.buf[0], L.ny, L.nstrip);
     double s = 0.0;
     if (i < L.nx && j < L.ny) {
         double u[4];
@@ -79,10 +79,10 @@ __global__ void __launch_bounds__(256) equilibrium_kernel(PhysArgs ph, LevelArgs
     if (i >= L.nx || j >= L.ny)
         return;
     const size_t plane = (size_t)L.nx * L.ny;
-    auto S = StateOf<PREC>::make(L.buf[buf], L.nx, L.ny);
+    auto S = StateOf<PREC>::make(L.buf[buf], L.ny, L.nstrip);
     const double amax = __longlong_as_double((long long)ctl.amax[L.ctl_off + m]);
     const double a = ph.kappa * 2.0 * amax / (1.0 - ph.alpha);
-    Phys P{ph.gamma, ph.alpha, (1.0 - ph.alpha) / 4.0, 1.0 / (2.0 * a), ph.rlmp_relax, ph.pos_eps};
+    const Phys P = make_phys(ph, a);
     double u[4], M[4][4];
 #pragma unroll
     for (int v = 0; v < 4; ++v)
@@ -280,10 +280,10 @@ __global__ void __launch_bounds__(256) step_ref_kernel(PhysArgs ph, LevelArgs L,
         ctl.a_last[r1 * nr + cm] = sc.a;
         ctl.amax[r2 * nr + cm] = 0ull;
     }
-    const Phys P{ph.gamma, ph.alpha, (1.0 - ph.alpha) / 4.0, 1.0 / (2.0 * sc.a), ph.rlmp_relax, ph.pos_eps};
+    const Phys P = make_phys(ph, sc.a);
     const size_t plane = (size_t)L.nx * L.ny;
-    auto Sin = StateOf<PREC>::make(L.buf[s & 1], L.nx, L.ny);
-    auto Sout = StateOf<PREC>::make(L.buf[(s + 1) & 1], L.nx, L.ny);
+    auto Sin = StateOf<PREC>::make(L.buf[s & 1], L.ny, L.nstrip);
+    auto Sout = StateOf<PREC>::make(L.buf[(s + 1) & 1], L.ny, L.nstrip);
     typedef typename StateOf<PREC>::type St;
     NodeAccess<St> A{Sin, m, L.nx, L.ny, ph.bc};
 
@@ -344,7 +344,7 @@ __global__ void __launch_bounds__(256) moments_kernel(PhysArgs ph, LevelArgs L, 
         return;
     const long long s = ctl.steps[phase * ctl.nr + L.ctl_off + m];
     const size_t plane = (size_t)L.nx * L.ny;
-    auto S = StateOf<PREC>::make(L.buf[s & 1], L.nx, L.ny);
+    auto S = StateOf<PREC>::make(L.buf[s & 1], L.ny, L.nstrip);
     const size_t n = (size_t)j * L.nx + i;
     const double rho = S.ld(0, 0, m, j, i), m1 = S.ld(1, 0, m, j, i), m2 = S.ld(2, 0, m, j, i), E = S.ld(3, 0, m, j, i);
     const double v1 = m1 / rho;
@@ -368,7 +368,7 @@ __global__ void __launch_bounds__(256) get_state_kernel(LevelArgs L, Ctl ctl, in
         return;
     const long long s = ctl.steps[phase * ctl.nr + L.ctl_off + m];
     const size_t plane = (size_t)L.nx * L.ny;
-    auto S = StateOf<PREC>::make(L.buf[s & 1], L.nx, L.ny);
+    auto S = StateOf<PREC>::make(L.buf[s & 1], L.ny, L.nstrip);
     const size_t n = (size_t)j * L.nx + i;
     for (int v = 0; v < 4; ++v)
         for (int sl = 0; sl < 5; ++sl)
@@ -385,7 +385,7 @@ __global__ void __launch_bounds__(256) set_macro_kernel(PhysArgs ph, LevelArgs L
     const int j = blockIdx.y * 4 + (threadIdx.x >> 6);
     const int m = blockIdx.z;
     const size_t plane = (size_t)L.nx * L.ny;
-    auto S = StateOf<PREC>::make(L.buf[0], L.nx, L.ny);
+    auto S = StateOf<PREC>::make(L.buf[0], L.ny, L.nstrip);
     double s = 0.0;
     if (i < L.nx && j < L.ny) {
         const size_t n = (size_t)j * L.nx + i;
@@ -431,7 +431,7 @@ __global__ void __launch_bounds__(256) stats_accumulate_kernel(PhysArgs ph, Leve
             mean[f] = sum[f] / (double)L.R;
         for (int m = 0; m < L.R; ++m) {
             const long long s = ctl.steps[phase * ctl.nr + L.ctl_off + m];
-            auto S = StateOf<PREC>::make(L.buf[s & 1], L.nx, L.ny);
+            auto S = StateOf<PREC>::make(L.buf[s & 1], L.ny, L.nstrip);
             double blk[3] = {0.0, 0.0, 0.0};
             for (int dj = 0; dj < r; ++dj)
                 for (int di = 0; di < r; ++di) {

@@ -52,8 +52,6 @@ struct MultiLevel {
     MarchArgs ma[MAX_LEVELS];
 };
 
-static constexpr int STRIP = 60;
-
 // Minimum resident blocks per CU the register allocation is held to (1 leaves
 // the full 512-entry register file to one wave per SIMD).
 #ifndef VLBM_MARCH_MIN_BLOCKS
@@ -114,12 +112,12 @@ __device__ __forceinline__ void march_item(const PhysArgs &ph, const LevelArgs &
         ctl.a_last[r1 * nr + cm] = sc.a;
         ctl.amax[r2 * nr + cm] = 0ull;
     }
-    const Phys P{ph.gamma, ph.alpha, (1.0 - ph.alpha) / 4.0, 1.0 / (2.0 * sc.a), ph.rlmp_relax, ph.pos_eps};
+    const Phys P = make_phys(ph, sc.a);
     const int nx = L.nx, ny = L.ny, bc = ph.bc, lim = ph.limiter;
     const bool periodic = bc == BC_PERIODIC;
     typedef typename StateOf<PREC>::type St;
-    const St Sin = StateOf<PREC>::make(L.buf[s & 1], nx, ny);
-    const St Sout = StateOf<PREC>::make(L.buf[(s + 1) & 1], nx, ny);
+    const St Sin = StateOf<PREC>::make(L.buf[s & 1], ny, L.nstrip);
+    const St Sout = StateOf<PREC>::make(L.buf[(s + 1) & 1], ny, L.nstrip);
     // Wave-uniform base of this realization in the input and output buffers;
     // a row of a plane sits at a 32-bit byte offset from it (a realization's
     // state is below 4 GiB), so every access is one scalar base plus the
@@ -127,7 +125,8 @@ __device__ __forceinline__ void march_item(const PhysArgs &ph, const LevelArgs &
     const char *const inb = Sin.real_base(m);
     char *const outb = Sout.real_base(m);
     const unsigned pitch = Sin.pitch;
-    auto row_off = [&](int j, int v, int sl) -> size_t { return (size_t)((unsigned)j * pitch + St::poff(nx, v, sl)); };
+    const int W = Sin.W;
+    auto row_off = [&](int j, int v, int sl) -> size_t { return (size_t)((unsigned)j * pitch + St::poff(W, v, sl)); };
 
     // ---- geometry of this lane ----
     const int c = strip * STRIP - 2 + lane; // column
@@ -154,9 +153,15 @@ __device__ __forceinline__ void march_item(const PhysArgs &ph, const LevelArgs &
             return true;
         return kind_col_interior && j >= 1 && j <= ny - 2;
     };
-    // lane column offsets within a row (loads read the clamped column cx)
-    auto col_in = [&](int v, int sl) -> unsigned { return (unsigned)cx * St::esize(v, sl); };
-    auto col_out = [&](int v, int sl) -> unsigned { return (unsigned)c * St::esize(v, sl); };
+    // Lane offsets within a plane row.  Loads read the slot of the clamped (or
+    // wrapped) column cx.  Stores cover the strip's 64 slots with all lanes --
+    // lane l writes slot (l - 2) mod 64, so lanes 2..61 (and lane 62 when it
+    // carries the last column) land on their columns and the halo lanes fill
+    // the unused slots -- and every store instruction writes whole lines.
+    const unsigned slot_in = col_slot(cx, L.nstrip);
+    const unsigned slot_out = (unsigned)(SLOTS * strip + ((lane - 2) & (SLOTS - 1)));
+    auto col_in = [&](int v, int sl) -> unsigned { return slot_in * St::esize(v, sl); };
+    auto col_out = [&](int v, int sl) -> unsigned { return slot_out * St::esize(v, sl); };
     double wmax = 0.0;
     int bad = 0;
     auto store_slot = [&](int sl, int j, const double x[4]) {
@@ -189,7 +194,8 @@ __device__ __forceinline__ void march_item(const PhysArgs &ph, const LevelArgs &
     };
     // a scheme row (not the inlet column) written at row j, duplicated into the
     // zero-gradient rows 0 / ny-1 when j is the adjacent interior row
-    auto row_stored = [&](int j) { return out_lane && !inlet_col && j >= y0 && j < y1 && (periodic || (j != 0 && j != ny - 1)); };
+    auto row_written = [&](int j) { return !inlet_col && j >= y0 && j < y1 && (periodic || (j != 0 && j != ny - 1)); };
+    auto row_stored = [&](int j) { return out_lane && row_written(j); };
     // (a level with ny = 3 duplicates its single interior row into both)
     auto dup_lo = [&](int j) { return !periodic && j == 1; };
     auto dup_hi = [&](int j) { return !periodic && j == ny - 2; };
@@ -197,7 +203,7 @@ __device__ __forceinline__ void march_item(const PhysArgs &ph, const LevelArgs &
     // ---- register ring ----
     // Row k-2, finished in iteration k: (u1+u2)+u3, the correction without its
     // north-face term, N_3 and M_3, the low-order state and its bounds.
-    double U1[4];
+    double U1[4], MC[4][4]; // row k-1 and its Maxwellians (formed in iteration k-1)
     double pC[4], cC[4], N3C[4], M3C[4], LC[4], bC[3];
     // Prefetch ring, two rows deep: buffer X_k holds the macroscopic row k and the
     // population row k-1 used by iteration k; it is refilled with X_{k+2} as soon
@@ -214,6 +220,7 @@ __device__ __forceinline__ void march_item(const PhysArgs &ph, const LevelArgs &
         pC[v] = cC[v] = N3C[v] = M3C[v] = LC[v] = 0.0;
     }
     bC[0] = bC[1] = bC[2] = 0.0;
+    maxwellians(P, U1, MC);
 
     const int k_first = y0 - 2, k_last = y1 + 1;
     // population row needed by iteration k is k-1; rows below y0-1 or above y1
@@ -242,22 +249,26 @@ __device__ __forceinline__ void march_item(const PhysArgs &ph, const LevelArgs &
 #pragma unroll
         for (int v = 0; v < 4; ++v)
             U0[v] = Ux[v];
-        // Row k-1: Maxwellians and non-equilibrium parts (its populations arrived).
+        // Row k-1: non-equilibrium parts (its populations arrived).
         double MB[4][4], NB[4][4];
-        maxwellians(P, U1, MB);
 #pragma unroll
         for (int q = 0; q < 4; ++q)
 #pragma unroll
-            for (int v = 0; v < 4; ++v)
+            for (int v = 0; v < 4; ++v) {
+                MB[q][v] = MC[q][v];
                 NB[q][v] = MB[q][v] - St::decode(v, 1 + q, Px[q][v]);
+            }
         load_x(k + 2, Ux, Px);
+        // Row k: Maxwellians, M_4 for the low-order state of row k-1 now, all
+        // four for the next iteration.
+        double MN[4][4];
+        maxwellians(P, U0, MN);
 
         // Low-order state and bounds of row k-1.
         const int jB = k - 1;
         double LB[4], bB[3];
         {
-            double M4n[4];
-            maxwellian4(P, U0, M4n); // row k
+            const double *M4n = MN[3]; // row k
             double M1w[4], M2e[4];
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
@@ -341,10 +352,11 @@ __device__ __forceinline__ void march_item(const PhysArgs &ph, const LevelArgs &
             }
             shuffle_copy(u4);
             shuffle_copy(u0);
-            if (row_stored(r)) {
+            if (row_stored(r))
+                account(u0);
+            if (row_written(r)) {
                 store_slot(0, r, u0);
                 store_slot(4, r, u4);
-                account(u0);
                 if (dup_lo(r)) {
                     store_slot(0, 0, u0);
                     store_slot(4, 0, u4);
@@ -374,7 +386,7 @@ __device__ __forceinline__ void march_item(const PhysArgs &ph, const LevelArgs &
             shuffle_copy(u1);
             shuffle_copy(u2);
             shuffle_copy(u3);
-            if (row_stored(jB)) {
+            if (row_written(jB)) {
                 store_slot(1, jB, u1);
                 store_slot(2, jB, u2);
                 store_slot(3, jB, u3);
@@ -404,6 +416,9 @@ __device__ __forceinline__ void march_item(const PhysArgs &ph, const LevelArgs &
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
             U1[v] = U0[v];
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                MC[q][v] = MN[q][v];
             pC[v] = pB[v];
             cC[v] = cB[v];
             N3C[v] = NB[2][v];

@@ -26,12 +26,23 @@ def test_library_exports_every_declared_symbol(lib):
     assert not missing, missing
 
 
+def _slots(nx, periodic=False):
+    """Element slots of a plane row: 64 per strip of 60 columns (a bounded level
+    of 60 q + 1 columns keeps q strips, the last one carrying 61 columns)."""
+    q = (nx - 1) // 60 if (not periodic and (nx - 1) % 60 == 0) else -(-nx // 60)
+    return 64 * q
+
+
 def test_state_bytes(lib):
     p = vlbm.Params.jet()
-    assert vlbm.vlbm_state_bytes(p, 128, 64, 8) == 20 * 8 * 128 * 64 * 8
+    assert _slots(128) == 192 and _slots(121) == 128 and _slots(121, True) == 192 and _slots(640) == 704
+    assert vlbm.vlbm_state_bytes(p, 128, 64, 8) == 8 * 64 * _slots(128) * 160
+    assert vlbm.vlbm_state_bytes(p, 121, 37, 3) == 3 * 37 * _slots(121) * 160
+    pp = vlbm.Params.jet(bc="periodic", kl_modes=0)
+    assert vlbm.vlbm_state_bytes(pp, 121, 37, 3) == 3 * 37 * _slots(121, True) * 160
     pm = vlbm.Params.jet(precision="mixed")
-    plane = 128 * 64 * 8
-    assert vlbm.vlbm_state_bytes(pm, 128, 64, 8) == 8 * plane * 8 + 12 * plane * 4
+    # 8 FP64 planes (u, E of the populations) and 12 FP32 planes: 112 B per slot
+    assert vlbm.vlbm_state_bytes(pm, 128, 64, 8) == 8 * 64 * _slots(128) * (8 * 8 + 12 * 4)
 
 
 @pytest.mark.parametrize("field,value", [("gamma", 1.0), ("alpha", 1.0), ("alpha", -0.1),
@@ -61,9 +72,9 @@ def test_realization_state_limit(lib):
     with pytest.raises(vlbm.VlbmError) as ei:
         vlbm.vlbm_state_bytes(vlbm.Params.jet(), 6000, 5000, 1)
     assert ei.value.code == vlbm.ERR_SIZE and "4 GiB" in vlbm.last_error()
-    assert vlbm.vlbm_state_bytes(vlbm.Params.jet(precision="mixed"), 6000, 5000, 1) == 112 * 6000 * 5000
+    assert vlbm.vlbm_state_bytes(vlbm.Params.jet(precision="mixed"), 6000, 5000, 1) == 112 * _slots(6000) * 5000
     # the largest configuration of the study (5056 x 2528) fits in FP64
-    assert vlbm.vlbm_state_bytes(vlbm.Params.jet(), 5056, 2528, 2) == 2 * 160 * 5056 * 2528
+    assert vlbm.vlbm_state_bytes(vlbm.Params.jet(), 5056, 2528, 2) == 2 * 160 * _slots(5056) * 2528
 
 
 def test_init_rejects_before_any_device_work(lib):
