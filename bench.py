@@ -97,6 +97,11 @@ def main() -> int:
     ap.add_argument("--workload", default="jet640")
     ap.add_argument("--chunk", type=int, default=240, help="launches per vlbm_step call")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="skip the autotuning pass (with --chunk-rows: a fixed step-kernel "
+                         "configuration, e.g. for a profiler run of this same command)")
+    ap.add_argument("--chunk-rows", type=int, default=0,
+                    help="rows per wave of the step kernel (0: autotuned / default)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run one device copy of known size (counter calibration)")
     ap.add_argument("--profile-launches", type=int, default=0,
@@ -135,6 +140,8 @@ def main() -> int:
         params = vlbm.Params.jet(precision=args.precision if args.precision != "both" else "fp64")
         level, bufs = make_level(params)
         h = vlbm.vlbm_init_ensemble(params, [level], coefs, R, stream)
+        if args.chunk_rows:
+            vlbm.vlbm_tune(h, "march", args.chunk_rows)
         vlbm.vlbm_step(h, w.t_final, args.profile_launches, want_done=True)
         vlbm.vlbm_destroy(h)
         a = torch.ones(1 << 28, dtype=torch.float64, device="cuda")
@@ -158,7 +165,8 @@ def main() -> int:
         w1m = torch.zeros(1, dtype=torch.float64, device="cuda")
         # Autotune on live steps of a first ensemble (outside the timed region);
         # later ensembles of the same shape reuse the cached choice.
-        tuned = [0]
+        tuned = [args.chunk_rows]
+        tune = tune and not args.no_tune
         if tune:
             h = vlbm.vlbm_init_ensemble(params, [level], coefs, R, stream)
             tuned = vlbm.vlbm_autotune(h, w.t_final, 4, 1)
@@ -170,6 +178,8 @@ def main() -> int:
 
         def one_step(k: int, timed: bool):
             h = vlbm.vlbm_init_ensemble(params, [level], coefs, R, stream)
+            if args.chunk_rows:
+                vlbm.vlbm_tune(h, "march", args.chunk_rows)
             done = False
             while not done:
                 if timed:
@@ -222,6 +232,26 @@ def main() -> int:
 
     variants = ["fp64", "mixed"] if args.precision == "both" else [args.precision]
     res = {v: run_variant(v) for v in variants}
+
+    def copy_bandwidth(nbytes: int = 1 << 31, reps: int = 5) -> float:
+        """Device-to-device copy rate (bytes read + written per second), the
+        practical HBM ceiling the step kernel is compared with."""
+        src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            dst.copy_(src)
+        e1.record(stream)
+        e1.synchronize()
+        gbs = 2 * nbytes * reps / (e0.elapsed_time(e1) / 1e3) / 1e9
+        del src, dst
+        torch.cuda.empty_cache()
+        return gbs
+
+    copy_gbs = copy_bandwidth()
     head = variants[0]
     r0 = res[head]
     out = {
@@ -242,7 +272,9 @@ def main() -> int:
                      "traffic": measured_traffic(head),
                      "kernel": "vlbm step kernel", "bytes_per_node_update": BYTES_PER_LUP[head],
                      "avg_launch_ms": round(r0["avg_launch_ms"], 5),
-                     "launches_per_pass": r0["launches_per_pass"]},
+                     "launches_per_pass": r0["launches_per_pass"],
+                     "device_copy_GBs": round(copy_gbs, 1),
+                     "frac_of_device_copy": round(r0["achieved"] / copy_gbs, 4)},
         "w1_rerun": r0["w1_rerun"],
     }
     def stat_errors(a, b):
@@ -270,7 +302,8 @@ def main() -> int:
                          "unit": "GB/s", "frac": round(rm["achieved"] / HBM_PEAK_GBS, 4),
                          "traffic": measured_traffic("mixed"),
                          "bytes_per_node_update": BYTES_PER_LUP["mixed"],
-                         "avg_launch_ms": round(rm["avg_launch_ms"], 5)},
+                         "avg_launch_ms": round(rm["avg_launch_ms"], 5),
+                         "frac_of_device_copy": round(rm["achieved"] / copy_gbs, 4)},
             "error_vs_fp64": stat_errors(res["fp64"], rm),
             "fp64_independent_ensemble_difference": stat_errors(res["fp64"], other),
             "time_steps_per_realization": rm["steps"],
