@@ -322,3 +322,84 @@ def w1(a: np.ndarray, b: np.ndarray) -> np.ndarray:
     if a.shape != b.shape:
         raise ValueError("equal ensemble sizes and grids required")
     return np.abs(np.sort(a, axis=0) - np.sort(b, axis=0)).sum(axis=0) / a.shape[0]
+
+
+# ---------------------------------------------------------------------------
+# Observables of the convergence study (Sec. 3.3-3.4) and the centreline
+# quantile diagnostics (Sec. 4, eq:empcdf, eq:widthratio).
+# ---------------------------------------------------------------------------
+
+def strong_error(coarse: np.ndarray, fine_r: np.ndarray) -> float:
+    """E_strong of eq:strongError.  coarse[m], fine_r[m]: density of realization m
+    on the common grid (the finer member already restricted); the relative L1
+    difference of each realization, averaged over the M realizations.  The cell
+    area of the L1 norms cancels in the ratio."""
+    if coarse.shape != fine_r.shape:
+        raise ValueError("same realizations and grid required")
+    M = coarse.shape[0]
+    total = 0.0
+    for m in range(M):
+        num = np.abs(coarse[m] - fine_r[m]).sum()
+        den = np.abs(fine_r[m]).sum()
+        total += num / den
+    return total / M
+
+
+def cell_mean_abs_diff(x: np.ndarray, y: np.ndarray) -> float:
+    """(1/N_x) sum_k |x_k - y_k| over the cells of the common grid: eq:mean when
+    x, y are the two ensemble-mean fields, eq:std when they are the two
+    standard-deviation fields."""
+    if x.shape != y.shape:
+        raise ValueError("same grid required")
+    return float(np.abs(x - y).sum() / x.size)
+
+
+def w11(a: np.ndarray, b: np.ndarray) -> float:
+    """W_{1,1} of eq:w1disc: the per-cell one-point W1 averaged over the cells."""
+    d = w1(a, b)
+    return float(d.sum() / d.size)
+
+
+def empirical_quantile(samples: np.ndarray, pct: int) -> np.ndarray:
+    """p_alpha of eq:empcdf, alpha = pct / 100 (integer percent in 1..100), per
+    cell (axis 0 = realizations): the smallest xi with hat F(xi) >= alpha.
+    hat F jumps only at sample values, so the infimum is a sample value; the
+    test hat F(xi) >= alpha is made exactly as 100 * #{x_m <= xi} >= pct * M,
+    with #{x_m <= s} counted by binary search in the sorted samples."""
+    if not 1 <= pct <= 100:
+        raise ValueError("pct must lie in 1..100")
+    M = samples.shape[0]
+    flat = samples.reshape(M, -1)
+    out = np.empty(flat.shape[1])
+    for c in range(flat.shape[1]):
+        s = np.sort(flat[:, c])
+        count = np.searchsorted(s, s, side="right")  # #{x_m <= s_(j)} for every j
+        j = int(np.argmax(100 * count >= pct * M))     # first j meeting the test
+        out[c] = s[j]
+    return out.reshape(samples.shape[1:])
+
+
+def width_ratio(samples: np.ndarray) -> np.ndarray:
+    """Q of eq:widthratio: (p95 - p5) / (p84 - p16) per cell."""
+    return (empirical_quantile(samples, 95) - empirical_quantile(samples, 5)) / \
+        (empirical_quantile(samples, 84) - empirical_quantile(samples, 16))
+
+
+def rate_fit(errors, dx) -> tuple[float, float]:
+    """(r, c) of eq:ratefit: least-squares line log E = r log dx + c."""
+    x = np.log(np.asarray(dx, dtype=np.float64))
+    y = np.log(np.asarray(errors, dtype=np.float64))
+    xm, ym = x.mean(), y.mean()
+    r = float(((x - xm) * (y - ym)).sum() / ((x - xm) ** 2).sum())
+    return r, float(ym - r * xm)
+
+
+def cauchy_pairs(L: int):
+    """eq:cauchy: (coarser level, finer level, level whose mesh width the error
+    is associated with) for l = 1..L: levels l-1 and l, mesh width of l-1."""
+    return [(l - 1, l, l - 1) for l in range(1, L + 1)]
+
+
+def reference_pairs(L: int):
+    """eq:ref: level l against the finest level L for l = 0..L-1, mesh width of l."""
+    return [(l, L, l) for l in range(L)]
