@@ -222,11 +222,64 @@ vlbm_status vlbm_sort_samples(double *samples, int64_t n_cells, int32_t m, void 
 /*
  * One-point Wasserstein-1 distance (eq:w1disc) between two sorted sample
  * stores of equal size [m][n_cells]: w1_cell[k] = (1/m) sum_m |a_(m) - b_(m)|
- * (DEVICE [n_cells] or NULL) and its average over cells (DEVICE scalar or
- * NULL).  Enqueued on hip_stream.
+ * (DEVICE [n_cells] or NULL) and its average over cells, W_{1,1} (DEVICE
+ * scalar or NULL; needs w1_cell, which it averages in a fixed order).
+ * Enqueued on hip_stream.
  */
 vlbm_status vlbm_w1(const double *sorted_a, const double *sorted_b, int64_t n_cells, int32_t m,
                     double *w1_cell, double *w1_mean, void *hip_stream);
+
+/* ---------------------------------------------------------------------------
+ * Observables of the convergence study (Sec. 3.3-3.4) and quantile diagnostics
+ * (Sec. 4).  Sample stores are laid out [m realizations][n_cells] as written by
+ * vlbm_ensemble_stats (restricted density of each realization on the common
+ * grid); "sorted" stores have been through vlbm_sort_samples.  Device pointers,
+ * asynchronous on hip_stream; every reduction runs in a fixed order, so equal
+ * inputs give equal bits.
+ * ------------------------------------------------------------------------- */
+#define VLBM_MAX_QUANTILES 8
+
+/*
+ * Strong pathwise error, eq:strongError: a and b are UNSORTED sample stores of
+ * the same realizations (same seeds) at two resolutions, both restricted to
+ * the common grid, b the finer member.  per_real[k] receives
+ * sum_c |a[k][c] - b[k][c]| / sum_c |b[k][c]| (device, [m]); out[0] their mean.
+ */
+vlbm_status vlbm_strong_error(const double *a, const double *b, int64_t n_cells, int32_t m,
+                              double *per_real, double *out, void *hip_stream);
+
+/*
+ * out[0] = (1/n) sum_i |x_i - y_i| over the n cells of the common grid: the
+ * error of eq:mean when x, y are the two ensemble-mean density fields, of
+ * eq:std for the two standard-deviation fields.  y = NULL gives (1/n) sum |x_i|.
+ */
+vlbm_status vlbm_mean_abs_diff(const double *x, const double *y, int64_t n, double *out,
+                               void *hip_stream);
+
+/*
+ * Empirical quantiles, eq:empcdf: for each pct[q] (HOST array of n_q <=
+ * VLBM_MAX_QUANTILES integer percents in 1..100) and each cell, the smallest
+ * sample xi with F(xi) >= pct/100, i.e. the order statistic ceil(pct m / 100)
+ * (1-based) of the cell's m sorted samples.  out: device [n_q][n_cells].
+ */
+vlbm_status vlbm_quantiles(const double *sorted, int64_t n_cells, int32_t m, const int32_t *pct,
+                           int32_t n_q, double *out, void *hip_stream);
+
+/*
+ * Quantile width ratio, eq:widthratio: q[c] = (p95 - p5) / (p84 - p16) per
+ * cell of a sorted store (IEEE result when p84 == p16: +inf, or NaN if also
+ * p95 == p5).  Gaussian laws give 1.654.
+ */
+vlbm_status vlbm_width_ratio(const double *sorted, int64_t n_cells, int32_t m, double *q,
+                             void *hip_stream);
+
+/*
+ * Convergence rate, eq:ratefit (host arithmetic): least-squares line
+ * log errors[i] = rate * log dx[i] + intercept over n >= 2 points; errors and
+ * dx HOST arrays of positive values, dx not all equal.  intercept may be NULL.
+ */
+vlbm_status vlbm_rate_fit(const double *errors, const double *dx, int32_t n, double *rate,
+                          double *intercept);
 
 /* Step kernel implementations (vlbm_tune). */
 #define VLBM_KERNEL_REFERENCE 0 /* one thread per node, neighbours recomputed        */

@@ -16,7 +16,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libvlbm_hip.so")
-SOURCES = ["vlbm_kernels.hip", "vlbm_step_march.hip", "vlbm_api.hip"]
+SOURCES = ["vlbm_kernels.hip", "vlbm_step_march.hip", "vlbm_observables.hip", "vlbm_api.hip"]
 ARCH = os.environ.get("VLBM_OFFLOAD_ARCH", "gfx950")
 
 

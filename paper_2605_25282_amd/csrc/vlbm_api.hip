@@ -46,6 +46,12 @@ __global__ void stats_finalize_kernel(const double *, long long, long long, doub
 template <int CPB> __global__ void sort_samples_kernel(double *, long long, int, int);
 __global__ void w1_kernel(const double *, const double *, long long, int, double *, double *);
 __global__ void scale_kernel(double *, double);
+void launch_mean_abs_diff(const double *x, const double *y, long long n, double *out, hipStream_t st);
+void launch_strong_error(const double *a, const double *b, long long ncell, int m, double *per_real,
+                         double *out, hipStream_t st);
+void launch_quantiles(const double *sorted, long long ncell, int m, const int *pct, int n_q, double *out,
+                      hipStream_t st);
+void launch_width_ratio(const double *sorted, long long ncell, int m, double *q, hipStream_t st);
 __global__ void fill_kernel(double *, double);
 } // namespace vlbm
 
@@ -724,13 +730,92 @@ vlbm_status vlbm_w1(const double *a, const double *b, int64_t n_cells, int32_t m
         return fail(VLBM_ERR_ARG, "sample stores must be non-NULL");
     if (n_cells < 1 || m < 1)
         return fail(VLBM_ERR_SIZE, "need n_cells >= 1 and m >= 1");
+    if (w1_mean && !w1_cell)
+        return fail(VLBM_ERR_ARG, "w1_mean needs w1_cell (the per-cell values are averaged in a fixed order)");
     hipStream_t st = (hipStream_t)hip_stream;
+    w1_kernel<<<(unsigned)((n_cells + 255) / 256), 256, 0, st>>>(a, b, n_cells, m, w1_cell, nullptr);
     if (w1_mean)
-        fill_kernel<<<1, 64, 0, st>>>(w1_mean, 0.0);
-    w1_kernel<<<(unsigned)((n_cells + 255) / 256), 256, 0, st>>>(a, b, n_cells, m, w1_cell, w1_mean);
-    if (w1_mean)
-        scale_kernel<<<1, 64, 0, st>>>(w1_mean, 1.0 / (double)n_cells);
+        launch_mean_abs_diff(w1_cell, nullptr, n_cells, w1_mean, st);
     LAUNCH_CHECK("w1");
+    return VLBM_OK;
+}
+
+vlbm_status vlbm_strong_error(const double *a, const double *b, int64_t n_cells, int32_t m, double *per_real,
+                              double *out, void *hip_stream)
+{
+    if (!a || !b || !per_real || !out)
+        return fail(VLBM_ERR_ARG, "a, b, per_real and out must be non-NULL");
+    if (n_cells < 1 || m < 1 || m > 1 << 24)
+        return fail(VLBM_ERR_SIZE, "need n_cells >= 1 and 1 <= m <= 2^24");
+    launch_strong_error(a, b, n_cells, m, per_real, out, (hipStream_t)hip_stream);
+    LAUNCH_CHECK("strong_error");
+    return VLBM_OK;
+}
+
+vlbm_status vlbm_mean_abs_diff(const double *x, const double *y, int64_t n, double *out, void *hip_stream)
+{
+    if (!x || !out)
+        return fail(VLBM_ERR_ARG, "x and out must be non-NULL");
+    if (n < 1)
+        return fail(VLBM_ERR_SIZE, "need n >= 1");
+    launch_mean_abs_diff(x, y, n, out, (hipStream_t)hip_stream);
+    LAUNCH_CHECK("mean_abs_diff");
+    return VLBM_OK;
+}
+
+vlbm_status vlbm_quantiles(const double *sorted, int64_t n_cells, int32_t m, const int32_t *pct, int32_t n_q,
+                           double *out, void *hip_stream)
+{
+    if (!sorted || !pct || !out)
+        return fail(VLBM_ERR_ARG, "sorted, pct and out must be non-NULL");
+    if (n_cells < 1 || m < 1)
+        return fail(VLBM_ERR_SIZE, "need n_cells >= 1 and m >= 1");
+    if (n_q < 1 || n_q > VLBM_MAX_QUANTILES)
+        return fail(VLBM_ERR_ARG, "n_q must lie in [1, %d] (got %d)", VLBM_MAX_QUANTILES, n_q);
+    for (int q = 0; q < n_q; ++q)
+        if (pct[q] < 1 || pct[q] > 100)
+            return fail(VLBM_ERR_ARG, "pct[%d] = %d outside [1, 100]", q, pct[q]);
+    launch_quantiles(sorted, n_cells, m, pct, n_q, out, (hipStream_t)hip_stream);
+    LAUNCH_CHECK("quantiles");
+    return VLBM_OK;
+}
+
+vlbm_status vlbm_width_ratio(const double *sorted, int64_t n_cells, int32_t m, double *q, void *hip_stream)
+{
+    if (!sorted || !q)
+        return fail(VLBM_ERR_ARG, "sorted and q must be non-NULL");
+    if (n_cells < 1 || m < 1)
+        return fail(VLBM_ERR_SIZE, "need n_cells >= 1 and m >= 1");
+    launch_width_ratio(sorted, n_cells, m, q, (hipStream_t)hip_stream);
+    LAUNCH_CHECK("width_ratio");
+    return VLBM_OK;
+}
+
+vlbm_status vlbm_rate_fit(const double *errors, const double *dx, int32_t n, double *rate, double *intercept)
+{
+    if (!errors || !dx || !rate)
+        return fail(VLBM_ERR_ARG, "errors, dx and rate must be non-NULL");
+    if (n < 2)
+        return fail(VLBM_ERR_SIZE, "need at least two points (got %d)", n);
+    double sx = 0.0, sy = 0.0;
+    for (int i = 0; i < n; ++i) {
+        if (!(errors[i] > 0.0) || !(dx[i] > 0.0) || !std::isfinite(errors[i]) || !std::isfinite(dx[i]))
+            return fail(VLBM_ERR_ARG, "errors and mesh widths must be finite and > 0 (point %d)", i);
+        sx += std::log(dx[i]);
+        sy += std::log(errors[i]);
+    }
+    const double mx = sx / n, my = sy / n;
+    double sxx = 0.0, sxy = 0.0;
+    for (int i = 0; i < n; ++i) {
+        const double u = std::log(dx[i]) - mx;
+        sxx += u * u;
+        sxy += u * (std::log(errors[i]) - my);
+    }
+    if (!(sxx > 0.0))
+        return fail(VLBM_ERR_ARG, "the mesh widths must not all be equal");
+    *rate = sxy / sxx;
+    if (intercept)
+        *intercept = my - *rate * mx;
     return VLBM_OK;
 }
 

@@ -95,6 +95,11 @@ def lib():
             "vlbm_stats_finalize": ([_VP, i64, i64, _VP, _VP, _VP], i32),
             "vlbm_sort_samples": ([_VP, i64, i32, _VP], i32),
             "vlbm_w1": ([_VP, _VP, i64, i32, _VP, _VP, _VP], i32),
+            "vlbm_strong_error": ([_VP, _VP, i64, i32, _VP, _VP, _VP], i32),
+            "vlbm_mean_abs_diff": ([_VP, _VP, i64, _VP, _VP], i32),
+            "vlbm_quantiles": ([_VP, i64, i32, ctypes.POINTER(i32), i32, _VP, _VP], i32),
+            "vlbm_width_ratio": ([_VP, i64, i32, _VP, _VP], i32),
+            "vlbm_rate_fit": ([_DP, _DP, i32, _DP, _DP], i32),
             "vlbm_tune": ([_VP, i32, i32], i32),
             "vlbm_autotune": ([_VP, dbl, i32, ctypes.POINTER(i32)], i32),
             "vlbm_destroy": ([_VP], i32),
@@ -193,6 +198,36 @@ def vlbm_sort_samples(samples, n_cells: int, m: int, stream=None) -> None:
 def vlbm_w1(a, b, n_cells: int, m: int, w1_cell=None, w1_mean=None, stream=None) -> None:
     _check(lib().vlbm_w1(_ptr(a), _ptr(b), n_cells, m, _ptr(w1_cell), _ptr(w1_mean),
                          _stream(stream)))
+
+
+def vlbm_strong_error(a, b, n_cells: int, m: int, per_real, out, stream=None) -> None:
+    _check(lib().vlbm_strong_error(_ptr(a), _ptr(b), n_cells, m, _ptr(per_real), _ptr(out),
+                                   _stream(stream)))
+
+
+def vlbm_mean_abs_diff(x, y, n: int, out, stream=None) -> None:
+    _check(lib().vlbm_mean_abs_diff(_ptr(x), _ptr(y), n, _ptr(out), _stream(stream)))
+
+
+def vlbm_quantiles(sorted_samples, n_cells: int, m: int, pct, out, stream=None) -> None:
+    pc = (ctypes.c_int32 * len(pct))(*[int(x) for x in pct])
+    _check(lib().vlbm_quantiles(_ptr(sorted_samples), n_cells, m, pc, len(pct), _ptr(out),
+                                _stream(stream)))
+
+
+def vlbm_width_ratio(sorted_samples, n_cells: int, m: int, q, stream=None) -> None:
+    _check(lib().vlbm_width_ratio(_ptr(sorted_samples), n_cells, m, _ptr(q), _stream(stream)))
+
+
+def vlbm_rate_fit(errors, dx) -> tuple[float, float]:
+    e = np.ascontiguousarray(errors, dtype=np.float64)
+    d = np.ascontiguousarray(dx, dtype=np.float64)
+    if e.shape != d.shape:
+        raise ValueError("errors and dx must have the same length")
+    r, c = ctypes.c_double(0.0), ctypes.c_double(0.0)
+    _check(lib().vlbm_rate_fit(e.ctypes.data_as(_DP), d.ctypes.data_as(_DP), len(e),
+                               ctypes.byref(r), ctypes.byref(c)))
+    return r.value, c.value
 
 
 KERNEL = {"reference": 0, "march": 1, "reference-eager": 0x100, "march-eager": 0x101}

@@ -103,3 +103,58 @@ def test_null_handles_rejected(lib):
     assert lib.vlbm_w1(None, None, 1, 1, None, None, None) == vlbm.ERR_ARG
     assert lib.vlbm_stats_finalize(None, 1, 1, None, None, None) == vlbm.ERR_ARG
     assert lib.vlbm_destroy(None) == vlbm.OK
+
+
+def test_rate_fit_reproduces_the_printed_tables(lib):
+    """The library's eq:ratefit (host arithmetic) reproduces every rate printed in
+    Tables 1-7 from the printed per-pair errors, and equals the oracle's fit."""
+    import os
+    import oracle as O
+    golden = os.path.join(os.path.dirname(__file__), "golden", "convergence_tables.txt")
+    blocks = {}
+    for line in open(golden):
+        if line.startswith("#") or not line.strip():
+            continue
+        t, proto, kind, a_, b_, *vals = line.split()
+        pairs, rates = blocks.setdefault((t, proto), ([], None))
+        if kind == "pair":
+            pairs.append((int(a_), [float(v) for v in vals]))
+        else:
+            blocks[(t, proto)] = (pairs, [float(v) for v in vals])
+    n = 0
+    for (t, proto), (pairs, rates) in blocks.items():
+        dx = [2.5 / nx for nx, _ in pairs]
+        for k in range(5):
+            errs = [v[k] for _, v in pairs]
+            r, c = vlbm.vlbm_rate_fit(errs, dx)
+            assert abs(r - rates[k]) <= 1.5e-3, (t, proto, k, r, rates[k])
+            ro, co = O.rate_fit(errs, dx)
+            assert r == pytest.approx(ro, rel=1e-14, abs=1e-15) and c == pytest.approx(co, rel=1e-14)
+            n += 1
+    assert n == 70
+
+
+def test_rate_fit_rejects_bad_input(lib):
+    for errs, dx in [([1.0], [0.1]), ([1.0, -1.0], [0.1, 0.05]), ([1.0, 2.0], [0.1, 0.1]),
+                     ([1.0, float("nan")], [0.1, 0.05]), ([1.0, 2.0], [0.0, 0.05])]:
+        with pytest.raises(vlbm.VlbmError):
+            vlbm.vlbm_rate_fit(errs, dx)
+
+
+def test_observable_entry_points_validate_before_launch(lib):
+    """Bad arguments are refused before anything touches a device."""
+    fake = ctypes.c_void_p(4096)
+    i32 = ctypes.c_int32
+    assert lib.vlbm_strong_error(None, fake, 10, 2, fake, fake, None) == vlbm.ERR_ARG
+    assert lib.vlbm_strong_error(fake, fake, 10, 2, None, fake, None) == vlbm.ERR_ARG
+    assert lib.vlbm_strong_error(fake, fake, 0, 2, fake, fake, None) == vlbm.ERR_SIZE
+    assert lib.vlbm_mean_abs_diff(None, None, 10, fake, None) == vlbm.ERR_ARG
+    assert lib.vlbm_mean_abs_diff(fake, None, 0, fake, None) == vlbm.ERR_SIZE
+    pct = (i32 * 3)(5, 50, 101)
+    assert lib.vlbm_quantiles(fake, 10, 4, pct, 3, fake, None) == vlbm.ERR_ARG
+    assert "101" in vlbm.last_error()
+    pct = (i32 * 9)(*([50] * 9))
+    assert lib.vlbm_quantiles(fake, 10, 4, pct, 9, fake, None) == vlbm.ERR_ARG
+    assert lib.vlbm_quantiles(fake, 0, 4, pct, 1, fake, None) == vlbm.ERR_SIZE
+    assert lib.vlbm_width_ratio(fake, 10, 0, fake, None) == vlbm.ERR_SIZE
+    assert lib.vlbm_w1(fake, fake, 10, 4, None, fake, None) == vlbm.ERR_ARG  # mean needs per-cell
