@@ -104,6 +104,10 @@ def main() -> int:
                     help="rows per wave of the step kernel (0: autotuned / default)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run one device copy of known size (counter calibration)")
+    ap.add_argument("--study", action="store_true",
+                    help="instead of the default line: the three-level ensemble (320x160, "
+                         "640x320, 1280x640, M=128, t=1e-3) advanced by one launch per step, "
+                         "then the Cauchy / reference convergence tables and rates")
     ap.add_argument("--profile-launches", type=int, default=0,
                     help="profiling mode: initial datum, this many step launches and a "
                          "2 GiB device copy, no statistics and no JSON line")
@@ -135,6 +139,9 @@ def main() -> int:
         lv = vlbm.Level(w.nx, w.ny, w.dx, w.y_min,
                         (vlbm._VP * 2)(bufs[0].data_ptr(), bufs[1].data_ptr()))
         return lv, bufs
+
+    if args.study:
+        return run_study(args, torch, vlbm, inputs)
 
     if args.profile_launches > 0:
         params = vlbm.Params.jet(precision=args.precision if args.precision != "both" else "fp64")
@@ -311,6 +318,74 @@ def main() -> int:
         }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w)
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+def run_study(args, torch, vlbm, inputs) -> int:
+    """Three nested levels of the jet with the same seeds in one ensemble: one
+    step of all levels is one launch; then the convergence study of Sec. 3.3-3.4
+    on the 320 x 160 common grid."""
+    import numpy as np
+
+    from paper_2605_25282_amd import convergence
+
+    precision = args.precision if args.precision != "both" else "fp64"
+    R, t_final = 128, 1e-3
+    shapes = [(320, 160), (640, 320), (1280, 640)]
+    levels = [(nx, ny, 1.0 / nx, -0.25) for nx, ny in shapes]
+    dx = [lv[2] for lv in levels]
+    coefs = inputs.kl_coefficients(inputs.DEFAULT_SEED, 0, R)
+    params = vlbm.Params.jet(precision=precision)
+    stream = torch.cuda.current_stream()
+    tuned = None
+    if not args.no_tune:
+        ens = vlbm.Ensemble(params, levels, coefs, R)
+        tuned = ens.autotune(t_final, 4)
+        ens.close()
+    ens = vlbm.Ensemble(params, levels, coefs, R)
+    if args.chunk_rows:
+        ens.tune("march", args.chunk_rows)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record(stream)
+    launches = ens.run(t_final, chunk=args.chunk)
+    e1.record(stream)
+    e1.synchronize()
+    step_s = e0.elapsed_time(e1) / 1e3
+    lups, steps = 0.0, []
+    for l, (nx, ny) in enumerate(shapes):
+        t, s, a, status = ens.times(l)
+        if np.any(status != 0) or np.any(t != t_final):
+            print(json.dumps({"error": f"level {l} did not reach t_final cleanly"}))
+            return 1
+        lups += float(s.sum()) * nx * ny
+        steps.append([int(s.min()), int(s.max())])
+    st = convergence.study(ens, dx, stream)
+    elapsed = time.perf_counter() - t0
+    ens.close()
+    bpl = BYTES_PER_LUP[precision]
+    out = {
+        "metric": METRIC, "value": round(lups / elapsed / 1e9, 4), "unit": "GLUPS", "n_gpus": 1,
+        "steps": 1, "warmup": 0, "ms_per_step": round(elapsed * 1e3, 3), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64" if precision == "fp64" else "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": f"three nested levels of the Mach-2000 jet (320x160, 640x320, 1280x640 on "
+                               f"[0,1]x[-0.25,0.25]), M={R} realizations each with the same seeds, to "
+                               f"t={t_final:g}, one launch per step of all levels, {precision}",
+                   "time_steps_per_realization": steps, "launches": launches,
+                   "step_kernel_rows_per_wave": tuned},
+        "roofline": {"bound": "hbm", "achieved": round(bpl * lups / step_s / 1e9, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(bpl * lups / step_s / 1e9 / HBM_PEAK_GBS, 4),
+                     "traffic": None, "kernel": "vlbm step kernel (all levels per launch)",
+                     "bytes_per_node_update": bpl, "avg_launch_ms": round(step_s * 1e3 / launches, 5)},
+        "study": {"common_grid": [320, 160], "dx": dx,
+                  "errors": {f"{p}/{o}": [float(f"{x:.6g}") for x in v] for (p, o), v in st.errors.items()},
+                  "pairs": {p: [[shapes[c][0], shapes[f][0]] for c, f, _ in v] for p, v in st.pairs.items()},
+                  "rates": {f"{p}/{o}": round(v, 4) for (p, o), v in st.rates.items()}},
+    }
     print(json.dumps(out), flush=True)
     return 0
 
