@@ -403,3 +403,48 @@ def cauchy_pairs(L: int):
 def reference_pairs(L: int):
     """eq:ref: level l against the finest level L for l = 0..L-1, mesh width of l."""
     return [(l, L, l) for l in range(L)]
+
+
+def subsample_indices(n: int, n_pd: int) -> np.ndarray:
+    """Cell indices of the n_pd-point subsample of one direction of the common
+    grid (Sec. 3.4, two-point construction): the cells containing the centres
+    of n_pd equal intervals, floor((2k + 1) n / (2 n_pd)), k = 0..n_pd-1."""
+    if not 1 <= n_pd <= n:
+        raise ValueError("need 1 <= n_pd <= n")
+    k = np.arange(n_pd)
+    return (2 * k + 1) * n // (2 * n_pd)
+
+
+def w1_2d(p: np.ndarray, q: np.ndarray) -> float:
+    """First Wasserstein distance with Euclidean ground cost between two
+    empirical laws of M points each in R^2 (rows of p and q), computed exactly
+    as the optimal assignment (an LP whose optimum is a permutation)."""
+    from scipy.optimize import linear_sum_assignment
+    if p.shape != q.shape or p.shape[1] != 2:
+        raise ValueError("two (M, 2) point sets required")
+    cost = np.sqrt((p[:, None, 0] - q[None, :, 0]) ** 2 + (p[:, None, 1] - q[None, :, 1]) ** 2)
+    rows, cols = linear_sum_assignment(cost)
+    total = 0.0
+    for i, j in zip(rows, cols):
+        total += cost[i, j]
+    return total / p.shape[0]
+
+
+def w12(a: np.ndarray, b: np.ndarray, n_pd: int = 10):
+    """W_{1,2} of eq:w2.  a, b: (M, ncy, ncx) density samples of the coarse and
+    the restricted fine ensemble on the common grid.  Subsample n_pd points per
+    direction (n_pd^2 cells), form for every ordered pair of retained cells
+    (k, k') the joint law of (rho(x_k), rho(x_k')) over the ensemble, and average
+    the 2-D W1 of the two laws over the P = n_pd^4 pairs.  Returns (mean,
+    per-pair values in pair order k * n_pd^2 + k', cells in row-major order)."""
+    M, ncy, ncx = a.shape
+    jy, ix = subsample_indices(ncy, n_pd), subsample_indices(ncx, n_pd)
+    cells = [(j, i) for j in jy for i in ix]
+    vals = []
+    for (j1, i1) in cells:
+        for (j2, i2) in cells:
+            p = np.stack([a[:, j1, i1], a[:, j2, i2]], axis=1)
+            q = np.stack([b[:, j1, i1], b[:, j2, i2]], axis=1)
+            vals.append(w1_2d(p, q))
+    vals = np.array(vals)
+    return float(vals.sum() / vals.size), vals

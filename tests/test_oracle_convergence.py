@@ -151,3 +151,50 @@ def test_width_ratio_of_gaussian_laws():
     # heavier tails raise Q (Student t with 3 degrees of freedom)
     tq = O.width_ratio(rng.standard_t(3, (20000, 1, 1)))[0, 0]
     assert tq > qn + 0.2
+
+
+@pytest.mark.parametrize("M", [1, 2, 3, 5, 7])
+def test_w1_2d_brute_force(M):
+    """The assignment optimum equals the minimum over all M! permutations (the
+    optimal coupling of two uniform M-point laws is a permutation)."""
+    import itertools
+    rng = np.random.default_rng(10 + M)
+    for _ in range(4):
+        p, q = rng.normal(size=(M, 2)), rng.gamma(2.0, 1.0, (M, 2))
+        best = min(sum(np.hypot(*(p[i] - q[s[i]])) for i in range(M)) for s in itertools.permutations(range(M)))
+        assert O.w1_2d(p, q) == pytest.approx(best / M, rel=1e-13)
+
+
+def test_w1_2d_special_cases():
+    rng = np.random.default_rng(11)
+    p = rng.normal(size=(40, 2))
+    # a rigid translation by d costs exactly |d| (triangle inequality bound is attained)
+    d = np.array([0.3, -1.2])
+    assert O.w1_2d(p, p + d) == pytest.approx(np.hypot(*d), rel=1e-13)
+    # points on the diagonal: Euclidean distance is sqrt(2)|x - y|, so W is sqrt(2) W1 of the values
+    x, y = rng.gamma(2.0, 1.0, 40), rng.normal(3.0, 1.0, 40)
+    pd_, qd = np.stack([x, x], 1), np.stack([y, y], 1)
+    assert O.w1_2d(pd_, qd) == pytest.approx(np.sqrt(2) * O.w1(x[:, None], y[:, None])[0], rel=1e-12)
+    # symmetric and zero on equal laws (any order)
+    q = rng.normal(size=(40, 2))
+    assert O.w1_2d(p, q) == pytest.approx(O.w1_2d(q, p), rel=1e-13)
+    assert O.w1_2d(p, p[rng.permutation(40)]) == 0.0
+
+
+def test_w12_structure():
+    """Subsample indices, pair count and symmetry of eq:w2."""
+    assert list(O.subsample_indices(100, 10)) == [5, 15, 25, 35, 45, 55, 65, 75, 85, 95]
+    assert list(O.subsample_indices(16, 4)) == [2, 6, 10, 14]
+    assert list(O.subsample_indices(7, 7)) == list(range(7))
+    rng = np.random.default_rng(12)
+    a = rng.gamma(2.0, 1.0, (6, 8, 12))
+    b = a + rng.normal(0.0, 0.1, a.shape)
+    mean, vals = O.w12(a, b, n_pd=3)
+    assert vals.size == 81 and mean == pytest.approx(vals.mean(), rel=1e-14)
+    v = vals.reshape(9, 9)
+    assert np.allclose(v, v.T, rtol=1e-13, atol=0)  # (k, k') and (k', k) are mirror laws
+    # diagonal pairs reduce to sqrt(2) x the one-point W1 of the retained cells
+    jy, ix = O.subsample_indices(8, 3), O.subsample_indices(12, 3)
+    diag = [np.sqrt(2) * O.w1(a[:, j:j + 1, i], b[:, j:j + 1, i])[0] for j in jy for i in ix]
+    assert np.allclose(np.diag(v), diag, rtol=1e-12, atol=0)
+    assert O.w12(a, a, n_pd=3)[0] == 0.0
