@@ -363,7 +363,7 @@ def run_study(args, torch, vlbm, inputs) -> int:
             return 1
         lups += float(s.sum()) * nx * ny
         steps.append([int(s.min()), int(s.max())])
-    st = convergence.study(ens, dx, stream)
+    st = convergence.study(ens, dx, 10, stream)
     elapsed = time.perf_counter() - t0
     ens.close()
     bpl = BYTES_PER_LUP[precision]

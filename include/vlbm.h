@@ -274,6 +274,24 @@ vlbm_status vlbm_width_ratio(const double *sorted, int64_t n_cells, int32_t m, d
                              void *hip_stream);
 
 /*
+ * Two-point Wasserstein distance, eq:w2.  a, b: UNSORTED sample stores
+ * [m][ncy * ncx] (row-major cells of the common grid) of the coarse and the
+ * restricted fine ensemble, same realizations.  The subsample keeps n_pd cells
+ * per direction, index floor((2k + 1) n / (2 n_pd)), k < n_pd (cell centres of
+ * n_pd equal intervals), cells numbered k = ky * n_pd + kx.  For every ordered
+ * pair (k, k') of the n_pd^2 retained cells, w_pair[k * n_pd^2 + k'] (device,
+ * [n_pd^4]) is the first Wasserstein distance with Euclidean cost between the
+ * laws of the m points (a[i][c_k], a[i][c_k']) and (b[i][c_k], b[i][c_k']),
+ * computed exactly as an optimal assignment (shortest augmenting paths); NaN
+ * when a sample is not finite.  w_mean (device scalar or NULL) is their
+ * average in a fixed order.  1 <= m <= VLBM_W12_MAX_SAMPLES, 1 <= n_pd <=
+ * min(ncx, ncy, 200).
+ */
+#define VLBM_W12_MAX_SAMPLES 1024
+vlbm_status vlbm_w12(const double *a, const double *b, int32_t ncx, int32_t ncy, int32_t m,
+                     int32_t n_pd, double *w_pair, double *w_mean, void *hip_stream);
+
+/*
  * Convergence rate, eq:ratefit (host arithmetic): least-squares line
  * log errors[i] = rate * log dx[i] + intercept over n >= 2 points; errors and
  * dx HOST arrays of positive values, dx not all equal.  intercept may be NULL.

@@ -3,9 +3,10 @@
 Composes C-ABI calls only: every level's moments are restricted on the device
 to the common (coarsest) grid (`vlbm_ensemble_stats`), giving its ensemble mean
 and standard deviation fields and the restricted density of every realization;
-the observables of each compared pair -- W_{1,1} (eq:w1disc), E_mean (eq:mean),
-E_std (eq:std), E_strong (eq:strongError) -- come from `vlbm_w1`,
-`vlbm_mean_abs_diff` and `vlbm_strong_error`, the pairs from the Cauchy
+the observables of each compared pair -- W_{1,1} (eq:w1disc), W_{1,2} (eq:w2),
+E_mean (eq:mean), E_std (eq:std), E_strong (eq:strongError) -- come from
+`vlbm_w1`, `vlbm_w12`, `vlbm_mean_abs_diff` and `vlbm_strong_error`, the pairs
+from the Cauchy
 (eq:cauchy) and reference (eq:ref) protocols, and the rates from
 `vlbm_rate_fit` (eq:ratefit).  This module only chooses pairs and allocates
 buffers.
@@ -16,7 +17,7 @@ from dataclasses import dataclass, field
 
 from . import vlbm
 
-OBSERVABLES = ("W11", "E_mean", "E_std", "E_strong")
+OBSERVABLES = ("W11", "W12", "E_mean", "E_std", "E_strong")
 
 
 def cauchy_pairs(L: int):
@@ -65,23 +66,28 @@ def level_stats(ens, level: int, r: int, stream=None) -> LevelStats:
     return LevelStats(mean, std, samples, srt)
 
 
-def pair_errors(a: LevelStats, b: LevelStats, n_cells: int, m: int, stream=None) -> dict:
-    """The four observables between a coarser member a and a finer member b."""
+def pair_errors(a: LevelStats, b: LevelStats, ncx: int, ncy: int, m: int, n_pd: int,
+                stream=None) -> dict:
+    """The five observables between a coarser member a and a finer member b."""
     import torch
-    out = torch.zeros(4, dtype=torch.float64, device="cuda")
+    n_cells = ncx * ncy
+    out = torch.zeros(5, dtype=torch.float64, device="cuda")
     w1c = torch.empty(n_cells, dtype=torch.float64, device="cuda")
     per = torch.empty(m, dtype=torch.float64, device="cuda")
+    w2p = torch.empty(n_pd ** 4, dtype=torch.float64, device="cuda")
     vlbm.vlbm_w1(a.sorted, b.sorted, n_cells, m, w1c, out[0:1], stream)
-    vlbm.vlbm_mean_abs_diff(a.mean[0], b.mean[0], n_cells, out[1:2], stream)
-    vlbm.vlbm_mean_abs_diff(a.std[0], b.std[0], n_cells, out[2:3], stream)
-    vlbm.vlbm_strong_error(a.samples, b.samples, n_cells, m, per, out[3:4], stream)
+    vlbm.vlbm_w12(a.samples, b.samples, ncx, ncy, m, n_pd, w2p, out[1:2], stream)
+    vlbm.vlbm_mean_abs_diff(a.mean[0], b.mean[0], n_cells, out[2:3], stream)
+    vlbm.vlbm_mean_abs_diff(a.std[0], b.std[0], n_cells, out[3:4], stream)
+    vlbm.vlbm_strong_error(a.samples, b.samples, n_cells, m, per, out[4:5], stream)
     vals = out.cpu().tolist()
     return dict(zip(OBSERVABLES, vals))
 
 
-def study(ens, dx, stream=None) -> Study:
+def study(ens, dx, n_pd: int = 10, stream=None) -> Study:
     """Cauchy and reference tables and rates over all levels of `ens` (levels
-    ordered coarse to fine, each a refinement of level 0 by an integer factor)."""
+    ordered coarse to fine, each a refinement of level 0 by an integer factor);
+    n_pd subsampled points per direction for W_{1,2} (the paper uses 10)."""
     L = len(ens.shapes) - 1
     nx0, ny0 = ens.shapes[0]
     stats = []
@@ -94,7 +100,7 @@ def study(ens, dx, stream=None) -> Study:
     st = Study(dx=list(dx), n_cells=n_cells, m=m)
     for proto, pairs in (("cauchy", cauchy_pairs(L)), ("reference", reference_pairs(L))):
         st.pairs[proto] = pairs
-        errs = [pair_errors(stats[c], stats[f], n_cells, m, stream) for c, f, _ in pairs]
+        errs = [pair_errors(stats[c], stats[f], nx0, ny0, m, n_pd, stream) for c, f, _ in pairs]
         for obs in OBSERVABLES:
             st.errors[(proto, obs)] = [e[obs] for e in errs]
             if len(pairs) >= 2:

@@ -52,6 +52,8 @@ void launch_strong_error(const double *a, const double *b, long long ncell, int 
 void launch_quantiles(const double *sorted, long long ncell, int m, const int *pct, int n_q, double *out,
                       hipStream_t st);
 void launch_width_ratio(const double *sorted, long long ncell, int m, double *q, hipStream_t st);
+void launch_w12(const double *a, const double *b, int ncx, int ncy, int m, int n_pd, double *w_pair,
+                double *w_mean, hipStream_t st);
 __global__ void fill_kernel(double *, double);
 } // namespace vlbm
 
@@ -788,6 +790,21 @@ vlbm_status vlbm_width_ratio(const double *sorted, int64_t n_cells, int32_t m, d
         return fail(VLBM_ERR_SIZE, "need n_cells >= 1 and m >= 1");
     launch_width_ratio(sorted, n_cells, m, q, (hipStream_t)hip_stream);
     LAUNCH_CHECK("width_ratio");
+    return VLBM_OK;
+}
+
+vlbm_status vlbm_w12(const double *a, const double *b, int32_t ncx, int32_t ncy, int32_t m, int32_t n_pd,
+                     double *w_pair, double *w_mean, void *hip_stream)
+{
+    if (!a || !b || !w_pair)
+        return fail(VLBM_ERR_ARG, "a, b and w_pair must be non-NULL");
+    if (ncx < 1 || ncy < 1 || m < 1 || m > VLBM_W12_MAX_SAMPLES)
+        return fail(VLBM_ERR_SIZE, "need ncx, ncy >= 1 and 1 <= m <= %d (got %d x %d, m = %d)",
+                    VLBM_W12_MAX_SAMPLES, ncx, ncy, m);
+    if (n_pd < 1 || n_pd > ncx || n_pd > ncy || n_pd > 200)
+        return fail(VLBM_ERR_ARG, "n_pd must lie in [1, min(ncx, ncy, 200)] (got %d)", n_pd);
+    launch_w12(a, b, ncx, ncy, m, n_pd, w_pair, w_mean, (hipStream_t)hip_stream);
+    LAUNCH_CHECK("w12");
     return VLBM_OK;
 }
 

@@ -94,6 +94,189 @@ __global__ void __launch_bounds__(256) width_ratio_kernel(const double *__restri
     q[c] = (p95 - p5) / (p84 - p16);
 }
 
+// ---------------------------------------------------------------------------
+// Two-point Wasserstein distance (eq:w2).  One workgroup per ordered pair of
+// subsampled cells (k, k'): the coarse law has the M points
+// P_i = (a[i][c_k], a[i][c_k']), the fine law Q_j = (b[j][c_k], b[j][c_k']), and
+// W = min over permutations s of (1/M) sum_i |P_i - Q_s(i)| (Euclidean cost).
+// Solved exactly by shortest augmenting paths with row / column potentials
+// (Hungarian method): row i is inserted by growing a Dijkstra tree over the
+// columns on reduced costs C(i0, j) - u(i0) - v(j) until an unmatched column is
+// reached, then the path is flipped.  Columns are owned by threads (their
+// potential, tentative distance, predecessor and tree flag stay in registers);
+// row potentials, the matching and the points sit in LDS.  The argmin over
+// columns breaks ties by the smallest column index, so every run gives the
+// same assignment.  Costs are recomputed from the points, sqrt(dx^2 + dy^2).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int subsample_index(int k, int n, int n_pd) { return (2 * k + 1) * n / (2 * n_pd); }
+
+template <int NT, int MAXC>
+__global__ void __launch_bounds__(NT) w12_kernel(const double *__restrict__ a, const double *__restrict__ b,
+                                                 int ncx, int ncy, int m, int n_pd, double *__restrict__ w_pair)
+{
+    extern __shared__ double lds_dyn[];
+    double *px = lds_dyn, *py = px + m, *u = py + m; // u[0..m]: row potentials (row 0 unused)
+    __shared__ double red_v[NT / 64];
+    __shared__ int red_j[NT / 64];
+    __shared__ int s_j1;
+    int *pm = (int *)(u + m + 1); // pm[j] = row matched to column j (1-based rows, 0 = none)
+    int *way = pm + m + 1;        // predecessor column of each column in the tree
+    const int pair = blockIdx.x, npts = n_pd * n_pd;
+    const int k1 = pair / npts, k2 = pair % npts;
+    const size_t ncell = (size_t)ncx * (size_t)ncy;
+    const size_t c1 = (size_t)subsample_index(k1 / n_pd, ncy, n_pd) * ncx + subsample_index(k1 % n_pd, ncx, n_pd);
+    const size_t c2 = (size_t)subsample_index(k2 / n_pd, ncy, n_pd) * ncx + subsample_index(k2 % n_pd, ncx, n_pd);
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+
+    // columns owned by this thread: j = 1 + t + c * NT
+    double qx[MAXC], qy[MAXC], v[MAXC], minv[MAXC];
+    bool used[MAXC];
+#pragma unroll
+    for (int c = 0; c < MAXC; ++c) {
+        const int j = 1 + t + c * NT;
+        qx[c] = qy[c] = v[c] = 0.0;
+        if (j <= m) {
+            qx[c] = b[(size_t)(j - 1) * ncell + c1];
+            qy[c] = b[(size_t)(j - 1) * ncell + c2];
+        }
+    }
+    for (int i = t; i < m; i += NT) {
+        px[i] = a[(size_t)i * ncell + c1];
+        py[i] = a[(size_t)i * ncell + c2];
+    }
+    for (int j = t; j <= m; j += NT) {
+        u[j] = 0.0;
+        pm[j] = 0;
+    }
+    __syncthreads();
+
+    bool failed = false; // non-finite samples: no valid augmenting column (uniform)
+    for (int row = 1; row <= m && !failed; ++row) {
+        if (t == 0)
+            pm[0] = row;
+#pragma unroll
+        for (int c = 0; c < MAXC; ++c) {
+            minv[c] = INFINITY;
+            used[c] = false;
+        }
+        int j0 = 0;
+        __syncthreads();
+        // the tree gains one matched column per pass, so a row needs at most row passes
+        for (int pass = 0;; ++pass) {
+            // column j0 joins the tree (column 0 is the virtual start)
+#pragma unroll
+            for (int c = 0; c < MAXC; ++c)
+                if (1 + t + c * NT == j0)
+                    used[c] = true;
+            const int i0 = pm[j0];
+            const double ux = px[i0 - 1], uy = py[i0 - 1], ui = u[i0];
+            double best = INFINITY;
+            int bj = 0x7fffffff;
+#pragma unroll
+            for (int c = 0; c < MAXC; ++c) {
+                const int j = 1 + t + c * NT;
+                if (j <= m && !used[c]) {
+                    const double dx = ux - qx[c], dy = uy - qy[c];
+                    const double cur = (sqrt(dx * dx + dy * dy) - ui) - v[c];
+                    if (cur < minv[c]) {
+                        minv[c] = cur;
+                        way[j] = j0;
+                    }
+                    if (minv[c] < best) { // columns of a thread ascend: ties keep the smaller j
+                        best = minv[c];
+                        bj = j;
+                    }
+                }
+            }
+            // block argmin, ties -> smallest column
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) {
+                const double ob = __shfl_xor(best, o, 64);
+                const int oj = __shfl_xor(bj, o, 64);
+                if (ob < best || (ob == best && oj < bj)) {
+                    best = ob;
+                    bj = oj;
+                }
+            }
+            if (NT > 64) {
+                if (lane == 0) {
+                    red_v[wv] = best;
+                    red_j[wv] = bj;
+                }
+                __syncthreads();
+                best = red_v[0];
+                bj = red_j[0];
+#pragma unroll
+                for (int w = 1; w < NT / 64; ++w)
+                    if (red_v[w] < best || (red_v[w] == best && red_j[w] < bj)) {
+                        best = red_v[w];
+                        bj = red_j[w];
+                    }
+            }
+            const double delta = best;
+            const int j1 = bj;
+            if (j1 < 1 || j1 > m || pass > m) { // only with NaN / infinite samples
+                failed = true;
+                break;
+            }
+            // potentials: tree columns and their rows move by delta, the others' distances drop
+            if (t == 0) {
+                u[pm[0]] += delta; // the virtual column 0 is always in the tree
+                s_j1 = j1;
+            }
+#pragma unroll
+            for (int c = 0; c < MAXC; ++c) {
+                const int j = 1 + t + c * NT;
+                if (j <= m) {
+                    if (used[c]) {
+                        u[pm[j]] += delta;
+                        v[c] -= delta;
+                    } else {
+                        minv[c] -= delta;
+                    }
+                }
+            }
+            __syncthreads();
+            j0 = s_j1;
+            if (pm[j0] == 0)
+                break;
+            __syncthreads();
+        }
+        if (failed)
+            break;
+        // flip the augmenting path back to the virtual column
+        if (t == 0) {
+            int j = j0;
+            while (j != 0) {
+                const int jp = way[j];
+                pm[j] = pm[jp];
+                j = jp;
+            }
+        }
+        __syncthreads();
+    }
+    if (failed) {
+        if (t == 0)
+            w_pair[pair] = NAN;
+        return;
+    }
+    // matched cost in row order: row i is matched to the column whose pm is i
+    int *col_of = way; // reuse: col_of[i] for rows 1..m
+    for (int j = 1 + t; j <= m; j += NT)
+        col_of[pm[j]] = j;
+    __syncthreads();
+    if (t == 0) {
+        double tot = 0.0;
+        for (int i = 1; i <= m; ++i) {
+            const int j = col_of[i];
+            const double dx = px[i - 1] - b[(size_t)(j - 1) * ncell + c1];
+            const double dy = py[i - 1] - b[(size_t)(j - 1) * ncell + c2];
+            tot += sqrt(dx * dx + dy * dy);
+        }
+        w_pair[pair] = tot / (double)m;
+    }
+}
+
 // 0-based index of the empirical quantile at pct percent of m samples:
 // ceil(pct m / 100) - 1, in exact integer arithmetic.
 __host__ __device__ inline int quantile_row(int pct, int m) { return (int)(((long long)pct * m + 99) / 100) - 1; }
@@ -121,6 +304,23 @@ void launch_quantiles(const double *sorted, long long ncell, int m, const int *p
     for (int q = 0; q < n_q; ++q)
         qa.k[q] = quantile_row(pct[q], m);
     quantile_kernel<<<(unsigned)((ncell + 255) / 256), 256, 0, st>>>(sorted, ncell, qa, out);
+}
+
+// LDS bytes of one two-point workgroup: points (2m), row potentials (m+1),
+// matching and predecessors (2 (m+1) ints)
+size_t w12_lds_bytes(int m) { return (size_t)(3 * m + 1) * sizeof(double) + (size_t)2 * (m + 1) * sizeof(int); }
+
+void launch_w12(const double *a, const double *b, int ncx, int ncy, int m, int n_pd, double *w_pair,
+                double *w_mean, hipStream_t st)
+{
+    const unsigned P = (unsigned)(n_pd * n_pd) * (unsigned)(n_pd * n_pd);
+    const size_t lds = w12_lds_bytes(m);
+    if (m <= 256)
+        w12_kernel<64, 4><<<P, 64, lds, st>>>(a, b, ncx, ncy, m, n_pd, w_pair);
+    else
+        w12_kernel<256, 4><<<P, 256, lds, st>>>(a, b, ncx, ncy, m, n_pd, w_pair);
+    if (w_mean)
+        mean_abs_diff_kernel<<<1, RED_THREADS, 0, st>>>(w_pair, nullptr, (long long)P, w_mean);
 }
 
 void launch_width_ratio(const double *sorted, long long ncell, int m, double *q, hipStream_t st)

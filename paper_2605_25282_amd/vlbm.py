@@ -100,6 +100,7 @@ def lib():
             "vlbm_quantiles": ([_VP, i64, i32, ctypes.POINTER(i32), i32, _VP, _VP], i32),
             "vlbm_width_ratio": ([_VP, i64, i32, _VP, _VP], i32),
             "vlbm_rate_fit": ([_DP, _DP, i32, _DP, _DP], i32),
+            "vlbm_w12": ([_VP, _VP, i32, i32, i32, i32, _VP, _VP, _VP], i32),
             "vlbm_tune": ([_VP, i32, i32], i32),
             "vlbm_autotune": ([_VP, dbl, i32, ctypes.POINTER(i32)], i32),
             "vlbm_destroy": ([_VP], i32),
@@ -217,6 +218,11 @@ def vlbm_quantiles(sorted_samples, n_cells: int, m: int, pct, out, stream=None) 
 
 def vlbm_width_ratio(sorted_samples, n_cells: int, m: int, q, stream=None) -> None:
     _check(lib().vlbm_width_ratio(_ptr(sorted_samples), n_cells, m, _ptr(q), _stream(stream)))
+
+
+def vlbm_w12(a, b, ncx: int, ncy: int, m: int, n_pd: int, w_pair, w_mean=None, stream=None) -> None:
+    _check(lib().vlbm_w12(_ptr(a), _ptr(b), ncx, ncy, m, n_pd, _ptr(w_pair), _ptr(w_mean),
+                          _stream(stream)))
 
 
 def vlbm_rate_fit(errors, dx) -> tuple[float, float]:

@@ -158,3 +158,9 @@ def test_observable_entry_points_validate_before_launch(lib):
     assert lib.vlbm_quantiles(fake, 0, 4, pct, 1, fake, None) == vlbm.ERR_SIZE
     assert lib.vlbm_width_ratio(fake, 10, 0, fake, None) == vlbm.ERR_SIZE
     assert lib.vlbm_w1(fake, fake, 10, 4, None, fake, None) == vlbm.ERR_ARG  # mean needs per-cell
+    assert lib.vlbm_w12(None, fake, 10, 10, 4, 3, fake, None, None) == vlbm.ERR_ARG
+    assert lib.vlbm_w12(fake, fake, 10, 10, 4, 3, None, None, None) == vlbm.ERR_ARG
+    assert lib.vlbm_w12(fake, fake, 10, 10, 1025, 3, fake, None, None) == vlbm.ERR_SIZE
+    assert lib.vlbm_w12(fake, fake, 10, 10, 0, 3, fake, None, None) == vlbm.ERR_SIZE
+    assert lib.vlbm_w12(fake, fake, 10, 2, 4, 3, fake, None, None) == vlbm.ERR_ARG  # n_pd > ncy
+    assert lib.vlbm_w12(fake, fake, 10, 10, 4, 0, fake, None, None) == vlbm.ERR_ARG

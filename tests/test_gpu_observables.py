@@ -1,10 +1,11 @@
 """GPU parity of the convergence-study observables and quantile diagnostics
-(eq:strongError, eq:mean, eq:std, eq:w1disc, eq:empcdf, eq:widthratio,
+(eq:strongError, eq:mean, eq:std, eq:w1disc, eq:w2, eq:empcdf, eq:widthratio,
 eq:cauchy, eq:ref, eq:ratefit) against the CPU oracle, through the C ABI.
 
 Bars: quantiles and the width ratio are selections / one correctly rounded
 expression, so bit-exact; reductions (strong error, cell means, W_{1,1}) differ
-from numpy only in summation order: 1e-12 relative.  Every input is seeded."""
+from numpy only in summation order, and W_{1,2}'s exact assignment from scipy's
+only in rounding: 1e-12 relative.  Every input is seeded."""
 import numpy as np
 import pytest
 
@@ -96,7 +97,7 @@ def test_convergence_study_matches_oracle():
     ens = vlbm.Ensemble(vlbm.Params.jet(), levels, coefs, R)
     assert ens.run(t_final, chunk=64) > 0
     dx = [lv[2] for lv in levels]
-    st = convergence.study(ens, dx)
+    st = convergence.study(ens, dx, n_pd=4)
     ens.close()
     # oracle: restricted density / speed / pressure per realization and level
     p = O.Params()
@@ -108,6 +109,7 @@ def test_convergence_study_matches_oracle():
         rho.append(O.restrict(r_, 1 << k))
     obs = {
         "W11": lambda a, b: O.w11(a, b),
+        "W12": lambda a, b: O.w12(a, b, n_pd=4)[0],
         "E_mean": lambda a, b: O.cell_mean_abs_diff(O.ensemble_mean(a), O.ensemble_mean(b)),
         "E_std": lambda a, b: O.cell_mean_abs_diff(O.ensemble_std(a), O.ensemble_std(b)),
         "E_strong": lambda a, b: O.strong_error(a, b),
@@ -120,3 +122,42 @@ def test_convergence_study_matches_oracle():
             assert all(e > 0 for e in ref)
             r_ref, _ = O.rate_fit(ref, [dx[w] for _, _, w in pairs])
             assert st.rates[(proto, name)] == pytest.approx(r_ref, rel=1e-8, abs=1e-10)
+
+
+@pytest.mark.parametrize("m,ncx,ncy,n_pd", [(1, 5, 4, 2), (7, 12, 8, 3), (64, 40, 20, 10),
+                                            (100, 33, 17, 4), (257, 20, 10, 3), (700, 16, 8, 2)])
+def test_two_point_wasserstein_vs_oracle(m, ncx, ncy, n_pd):
+    """eq:w2: exact assignment per ordered pair of subsampled cells, single-wave
+    solver (m <= 256) and four-wave solver (m > 256), against scipy's
+    assignment in the oracle; the paper's n_pd = 10 included."""
+    a = inputs.random_fields(900 + m, (m, ncy, ncx))
+    b = a * (1.0 + 0.3 * inputs.random_fields(901 + m, (m, ncy, ncx), -1.0, 1.0))
+    P = n_pd ** 4
+    wp = torch.empty(P, dtype=torch.float64, device="cuda")
+    wm = torch.zeros(1, dtype=torch.float64, device="cuda")
+    vlbm.vlbm_w12(_dev(a), _dev(b), ncx, ncy, m, n_pd, wp, wm)
+    torch.cuda.synchronize()
+    ref_mean, ref_vals = O.w12(a, b, n_pd=n_pd)
+    assert np.allclose(wp.cpu().numpy(), ref_vals, rtol=1e-12, atol=1e-15)
+    assert wm.item() == pytest.approx(ref_mean, rel=1e-12)
+
+
+def test_two_point_wasserstein_degenerate_inputs():
+    """Equal laws give 0 (every pair); a non-finite sample gives NaN for the
+    pairs that use its cells and leaves the others exact."""
+    m, ncx, ncy, n_pd = 16, 6, 6, 3
+    a = inputs.random_fields(5, (m, ncy, ncx))
+    wp = torch.empty(n_pd ** 4, dtype=torch.float64, device="cuda")
+    vlbm.vlbm_w12(_dev(a), _dev(a[::-1].copy()), ncx, ncy, m, n_pd, wp)
+    torch.cuda.synchronize()
+    assert np.all(wp.cpu().numpy() == 0.0)
+    bad = a.copy()
+    bad[3, 1, 1] = np.nan  # cell (1, 1) is retained: index floor(3 * 6 / 6) = 1 -> yes
+    vlbm.vlbm_w12(_dev(bad), _dev(a), ncx, ncy, m, n_pd, wp)
+    torch.cuda.synchronize()
+    got = wp.cpu().numpy().reshape(9, 9)
+    k = 0  # retained cells (1,1),(1,3),(1,5),(3,1),... ; (1,1) is k = 0
+    assert np.all(np.isnan(got[k, :])) and np.all(np.isnan(got[:, k]))
+    ok = np.ones((9, 9), bool)
+    ok[k, :] = ok[:, k] = False
+    assert np.all(np.isfinite(got[ok]))
