@@ -108,6 +108,10 @@ def main() -> int:
                     help="instead of the default line: the three-level ensemble (320x160, "
                          "640x320, 1280x640, M=128, t=1e-3) advanced by one launch per step, "
                          "then the Cauchy / reference convergence tables and rates")
+    ap.add_argument("--study-geometry", default="config", choices=["config", "paper"],
+                    help="paper: the paper's domain [0,2.5]x[-1,1] with grids 500x400, 1000x800, "
+                         "2000x1600 and the study at t = 0.0005 k, k = 1..7")
+    ap.add_argument("--study-m", type=int, default=0, help="realizations (0: 128 config, 32 paper)")
     ap.add_argument("--profile-launches", type=int, default=0,
                     help="profiling mode: initial datum, this many step launches and a "
                          "2 GiB device copy, no statistics and no JSON line")
@@ -323,68 +327,85 @@ def main() -> int:
 
 
 def run_study(args, torch, vlbm, inputs) -> int:
-    """Three nested levels of the jet with the same seeds in one ensemble: one
-    step of all levels is one launch; then the convergence study of Sec. 3.3-3.4
-    on the 320 x 160 common grid."""
+    """Nested levels of the jet with the same seeds in one ensemble: one step of
+    all levels is one launch; at each checkpoint the convergence study of
+    Sec. 3.3-3.4 on the coarsest (common) grid."""
     import numpy as np
 
     from paper_2605_25282_amd import convergence
 
     precision = args.precision if args.precision != "both" else "fp64"
-    R, t_final = 128, 1e-3
-    shapes = [(320, 160), (640, 320), (1280, 640)]
-    levels = [(nx, ny, 1.0 / nx, -0.25) for nx, ny in shapes]
-    dx = [lv[2] for lv in levels]
+    if args.study_geometry == "paper":
+        works = [inputs.PAPER_GRIDS[f"paper{nx}"] for nx in (500, 1000, 2000)]
+        R = args.study_m or 32
+        checkpoints = list(inputs.PAPER_CHECKPOINTS)
+        geometry = "the paper's domain [0,2.5]x[-1,1]"
+    else:
+        works = [inputs.WORKLOADS[n] for n in ("jet320", "jet640", "jet1280")]
+        R = args.study_m or 128
+        checkpoints = [1e-3]
+        geometry = "[0,1]x[-0.25,0.25]"
+    shapes = [(w.nx, w.ny) for w in works]
+    levels = [(w.nx, w.ny, w.dx, w.y_min) for w in works]
+    dx = [w.dx for w in works]
     coefs = inputs.kl_coefficients(inputs.DEFAULT_SEED, 0, R)
     params = vlbm.Params.jet(precision=precision)
     stream = torch.cuda.current_stream()
     tuned = None
     if not args.no_tune:
         ens = vlbm.Ensemble(params, levels, coefs, R)
-        tuned = ens.autotune(t_final, 4)
+        tuned = ens.autotune(checkpoints[0], 4)
         ens.close()
     ens = vlbm.Ensemble(params, levels, coefs, R)
     if args.chunk_rows:
         ens.tune("march", args.chunk_rows)
     torch.cuda.synchronize()
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
     t0 = time.perf_counter()
-    e0.record(stream)
-    launches = ens.run(t_final, chunk=args.chunk)
-    e1.record(stream)
-    e1.synchronize()
-    step_s = e0.elapsed_time(e1) / 1e3
-    lups, steps = 0.0, []
-    for l, (nx, ny) in enumerate(shapes):
-        t, s, a, status = ens.times(l)
-        if np.any(status != 0) or np.any(t != t_final):
-            print(json.dumps({"error": f"level {l} did not reach t_final cleanly"}))
-            return 1
-        lups += float(s.sum()) * nx * ny
-        steps.append([int(s.min()), int(s.max())])
-    st = convergence.study(ens, dx, 10, stream)
+    step_s, launches, lups, rows = 0.0, 0, 0.0, []
+    prev = np.zeros((len(levels), R))
+    for tc in checkpoints:
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        launches += ens.run(tc, chunk=args.chunk)
+        e1.record(stream)
+        e1.synchronize()
+        step_s += e0.elapsed_time(e1) / 1e3
+        steps = []
+        for l, (nx, ny) in enumerate(shapes):
+            t, s, a, status = ens.times(l)
+            if np.any(status != 0) or np.any(t != tc):
+                print(json.dumps({"error": f"level {l} did not reach t = {tc:g} cleanly"}))
+                return 1
+            lups += float((s - prev[l]).sum()) * nx * ny
+            prev[l] = s
+            steps.append([int(s.min()), int(s.max())])
+        st = convergence.study(ens, dx, 10, stream)
+        rows.append({"t": tc, "time_steps_per_realization": steps,
+                     "errors": {f"{p}/{o}": [float(f"{x:.6g}") for x in v] for (p, o), v in st.errors.items()},
+                     "rates": {f"{p}/{o}": round(v, 4) for (p, o), v in st.rates.items()}})
     elapsed = time.perf_counter() - t0
     ens.close()
     bpl = BYTES_PER_LUP[precision]
+    grids = ", ".join(f"{nx}x{ny}" for nx, ny in shapes)
     out = {
         "metric": METRIC, "value": round(lups / elapsed / 1e9, 4), "unit": "GLUPS", "n_gpus": 1,
         "steps": 1, "warmup": 0, "ms_per_step": round(elapsed * 1e3, 3), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f64" if precision == "fp64" else "f32+f64",
         "data": "synthetic",
-        "config": {"workload": f"three nested levels of the Mach-2000 jet (320x160, 640x320, 1280x640 on "
-                               f"[0,1]x[-0.25,0.25]), M={R} realizations each with the same seeds, to "
-                               f"t={t_final:g}, one launch per step of all levels, {precision}",
-                   "time_steps_per_realization": steps, "launches": launches,
-                   "step_kernel_rows_per_wave": tuned},
+        "config": {"workload": f"nested levels of the Mach-2000 jet ({grids} on {geometry}), M={R} "
+                               f"realizations each with the same seeds, to t={checkpoints[-1]:g}, one "
+                               f"launch per step of all levels, {precision}",
+                   "launches": launches, "step_kernel_rows_per_wave": tuned},
         "roofline": {"bound": "hbm", "achieved": round(bpl * lups / step_s / 1e9, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(bpl * lups / step_s / 1e9 / HBM_PEAK_GBS, 4),
                      "traffic": None, "kernel": "vlbm step kernel (all levels per launch)",
                      "bytes_per_node_update": bpl, "avg_launch_ms": round(step_s * 1e3 / launches, 5)},
-        "study": {"common_grid": [320, 160], "dx": dx,
-                  "errors": {f"{p}/{o}": [float(f"{x:.6g}") for x in v] for (p, o), v in st.errors.items()},
-                  "pairs": {p: [[shapes[c][0], shapes[f][0]] for c, f, _ in v] for p, v in st.pairs.items()},
-                  "rates": {f"{p}/{o}": round(v, 4) for (p, o), v in st.rates.items()}},
+        "study": {"common_grid": list(shapes[0]), "dx": dx, "n_pd": 10,
+                  "pairs": {p: [[shapes[c][0], shapes[f][0]] for c, f, _ in v]
+                            for p, v in (("cauchy", convergence.cauchy_pairs(len(shapes) - 1)),
+                                         ("reference", convergence.reference_pairs(len(shapes) - 1)))},
+                  "checkpoints": rows},
     }
     print(json.dumps(out), flush=True)
     return 0

@@ -87,4 +87,12 @@ WORKLOADS = {
     "jet5056": JetWorkload("jet5056", 5056, 2528, 1000, 1e-3),
 }
 
+# The paper's own study (Sec. 3.3): domain [0, 2.5] x [-1, 1], four nested grids,
+# M = 1000, statistics at t = 0.0005 k, k = 1..7.
+PAPER_GRIDS = {
+    f"paper{nx}": JetWorkload(f"paper{nx}", nx, nx * 4 // 5, 1000, 0.0035, x_len=2.5, y_min=-1.0)
+    for nx in (500, 1000, 2000, 4000)
+}
+PAPER_CHECKPOINTS = tuple(0.0005 * k for k in range(1, 8))
+
 DEFAULT_SEED = 2605
