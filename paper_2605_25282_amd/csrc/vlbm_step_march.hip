@@ -5,19 +5,23 @@
 // realization and one chunk of rows; lanes 2..61 produce the strip's 60
 // output columns, lanes 0, 1, 62, 63 are the halo the radius-2 stencil needs.
 // The wave marches up its rows.  Iteration k reads the macroscopic row k and
-// the population row k-1 (both prefetched one iteration ahead) and
-//   - forms the Maxwellians (eq:maxwellians12-34) and non-equilibrium parts
-//     N = M - u_k of row k-1, its low-order state, density bounds and the
-//     blending parameter of its east x-face,
+// the population row k-1 (both prefetched two iterations ahead) and
+//   - forms the Maxwellians (eq:maxwellians12-34) of row k, which serve as
+//     M_4 of the low-order state of row k-1 now and as the Maxwellians of
+//     row k in the next iteration,
+//   - forms the non-equilibrium parts N = M - u_k of row k-1, its low-order
+//     state, density bounds and the blending parameter of its east x-face,
 //   - forms the blending parameter of the y-face between rows k-2 and k-1,
 //   - finishes row k-2 (u_4 and u of eq:vlbm4-5) and
 //   - writes u_1..u_3 of row k-1 (eq:vlbm1-3), which no longer depend on
 //     anything unknown, keeping only the partial sums of eq:vlbm5.
-// Only four 4-vectors per node (partial sum, partial correction, N_3, M_3)
-// plus the low-order state travel to the next iteration.
-// x-neighbours are exchanged with DPP lane shifts.  Each value of the state is
-// read from HBM once (plus the 4-column and 4-row halos) and written once:
-// 320 B per FP64 node update.
+// Only four 4-vectors per node (partial sum, partial correction, N_3, M_3),
+// the low-order state and the Maxwellians of the newest row travel to the
+// next iteration.  x-neighbours are exchanged with DPP lane shifts.  Each
+// value of the state is read from memory once (plus the 2-column and 2-row
+// halos of the stencil) and written once, each store instruction covering
+// the strip's whole 64-slot block of a plane row (see the layout in
+// vlbm_device.h): 320 B per FP64 node update.
 //
 // Every arithmetic expression has the operand order of the reference form in
 // vlbm_kernels.hip (and of the oracle), so the result is bitwise identical.
@@ -25,10 +29,10 @@
 // Boundary layers (Dirichlet inlet column, zero-gradient copy columns and
 // rows) are produced by the wave that owns the copied interior node.
 //
-// Work items (realization, row chunk, strip) are ordered strip-fastest and
-// dealt round-robin to a grid sized to the resident capacity of the chip;
-// blocks are renumbered so that consecutive items land on one XCD (shared L2
-// for the halo re-reads of neighbouring strips and chunks).
+// Work items (realization, row chunk, strip) of every mesh level are ordered
+// strip-fastest and dealt round-robin to a grid sized to the resident
+// capacity of the chip; blocks are renumbered so that consecutive items land
+// on one XCD (shared L2 for the halo re-reads of neighbouring strips).
 #include "vlbm_device.h"
 
 namespace vlbm {
@@ -192,8 +196,11 @@ __device__ __forceinline__ void march_item(const PhysArgs &ph, const LevelArgs &
             }
         }
     };
-    // a scheme row (not the inlet column) written at row j, duplicated into the
-    // zero-gradient rows 0 / ny-1 when j is the adjacent interior row
+    // Row j of the chunk is stored by every lane but the inlet column's (written
+    // on its own, after the scheme values of its row); it is duplicated into
+    // the zero-gradient rows 0 / ny-1 when it is the adjacent interior row.
+    // The stored values of the output lanes also enter the wave-speed maximum
+    // and the admissibility check.
     auto row_written = [&](int j) { return !inlet_col && j >= y0 && j < y1 && (periodic || (j != 0 && j != ny - 1)); };
     auto row_stored = [&](int j) { return out_lane && row_written(j); };
     // (a level with ny = 3 duplicates its single interior row into both)
