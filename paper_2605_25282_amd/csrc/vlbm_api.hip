@@ -24,18 +24,6 @@ namespace vlbm {
 template <int PREC> __global__ void init_macro_kernel(PhysArgs, LevelArgs, const double *, Ctl);
 template <int PREC> __global__ void equilibrium_kernel(PhysArgs, LevelArgs, Ctl, int);
 template <int PREC> __global__ void step_ref_kernel(PhysArgs, LevelArgs, Ctl, int, double);
-struct MarchArgs {
-    int nstrip, chunk, nchunk, lane62_last;
-};
-static constexpr int MAX_LEVELS = 8;
-struct MultiLevel {
-    int nlev;
-    int nblocks;
-    int per_xcd;
-    long long item_off[MAX_LEVELS + 1];
-    LevelArgs L[MAX_LEVELS];
-    MarchArgs ma[MAX_LEVELS];
-};
 template <int PREC> __global__ void step_march_kernel(PhysArgs, MultiLevel, Ctl, int, double);
 template <int PREC> __global__ void moments_kernel(PhysArgs, LevelArgs, Ctl, int, double *, double *, double *);
 template <int PREC> __global__ void get_state_kernel(LevelArgs, Ctl, int, double *);
@@ -197,7 +185,6 @@ namespace {
 
 int phase_of(const vlbm_ensemble *e) { return (int)(e->n_launch % 3); }
 
-// Work decomposition of the marching kernel for one level.
 // Strips of the marching kernel = column strips of the state layout; lane 62 of
 // the last strip carries the last column of a bounded level of 60 q + 1 columns.
 int strips_of(const vlbm_ensemble *e, const LevelArgs &L, int *lane62)

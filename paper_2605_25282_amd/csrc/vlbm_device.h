@@ -506,6 +506,26 @@ template <> struct StateOf<1> {
     __device__ static type make(void *b, int ny, int nstrip) { return StateMixed::make(b, ny, nstrip); }
 };
 
+// Work decomposition of the marching step kernel for one level.
+struct MarchArgs {
+    int nstrip;      // column strips per realization (the layout's strips)
+    int chunk;       // rows per work item
+    int nchunk;      // row chunks per realization
+    int lane62_last; // 1: lane 62 of the last strip writes the copy column nx-1
+};
+
+// All mesh levels advanced by one launch: work items are concatenated level by
+// level (realization, row chunk, strip within a level).
+static constexpr int MAX_LEVELS = 8;
+struct MultiLevel {
+    int nlev;
+    int nblocks;                   // logical blocks (4 waves each) of the grid
+    int per_xcd;                   // logical blocks per XCD slot
+    long long item_off[MAX_LEVELS + 1];
+    LevelArgs L[MAX_LEVELS];
+    MarchArgs ma[MAX_LEVELS];
+};
+
 // Node kinds of reading R8: 0 interior, 1 Dirichlet inlet layer, 2 copy layer.
 __device__ __forceinline__ int node_kind(int bc, int nx, int ny, int i, int j)
 {

@@ -37,25 +37,6 @@
 
 namespace vlbm {
 
-struct MarchArgs {
-    int nstrip;      // column strips per realization
-    int chunk;       // rows per work item
-    int nchunk;      // row chunks per realization
-    int lane62_last; // 1: lane 62 of the last strip writes the copy column nx-1
-};
-
-// All mesh levels advanced by one launch: work items are concatenated level by
-// level (realization, row chunk, strip within a level).
-static constexpr int MAX_LEVELS = 8;
-struct MultiLevel {
-    int nlev;
-    int nblocks;                   // logical blocks (4 waves each) of the grid
-    int per_xcd;                   // logical blocks per XCD slot
-    long long item_off[MAX_LEVELS + 1];
-    LevelArgs L[MAX_LEVELS];
-    MarchArgs ma[MAX_LEVELS];
-};
-
 // Minimum resident blocks per CU the register allocation is held to (1 leaves
 // the full 512-entry register file to one wave per SIMD).
 #ifndef VLBM_MARCH_MIN_BLOCKS
