@@ -10,8 +10,11 @@
  * dt = dx / a_n with the kinetic speed re-evaluated every step (Sec. 2.3),
  * and computes the ensemble statistics of Sec. 3 on the device: conservative
  * restriction (Sec. 3.2), per-cell mean (eq:mean), population standard
- * deviation (eq:std) and the one-point Wasserstein-1 distance from sorted
- * samples (eq:w1disc).
+ * deviation (eq:std), the one-point Wasserstein-1 distance from sorted
+ * samples (eq:w1disc), the two-point distance (eq:w2), the strong pathwise
+ * error (eq:strongError), empirical quantiles and their width ratio
+ * (eq:empcdf, eq:widthratio), and the convergence-rate fit (eq:ratefit).
+ * Several mesh levels of one ensemble advance together, one launch per step.
  *
  * Conventions for every entry point:
  *   - The return value is a vlbm_status: VLBM_OK (0) or a negative code.
