@@ -238,9 +238,12 @@ __global__ void __launch_bounds__(NT) w12_kernel(const double *__restrict__ a, c
             }
             __syncthreads();
             j0 = s_j1;
-            if (pm[j0] == 0)
-                break;
+            const bool reached_free = pm[j0] == 0;
+            // every thread has read pm[j0] before thread 0 flips the path (which
+            // rewrites pm) or any thread starts the next pass
             __syncthreads();
+            if (reached_free)
+                break;
         }
         if (failed)
             break;
@@ -269,6 +272,10 @@ __global__ void __launch_bounds__(NT) w12_kernel(const double *__restrict__ a, c
         double tot = 0.0;
         for (int i = 1; i <= m; ++i) {
             const int j = col_of[i];
+            if (j < 1 || j > m) { // not a permutation: never read memory with it
+                tot = NAN;
+                break;
+            }
             const double dx = px[i - 1] - b[(size_t)(j - 1) * ncell + c1];
             const double dy = py[i - 1] - b[(size_t)(j - 1) * ncell + c2];
             tot += sqrt(dx * dx + dy * dy);

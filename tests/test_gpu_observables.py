@@ -125,7 +125,7 @@ def test_convergence_study_matches_oracle():
 
 
 @pytest.mark.parametrize("m,ncx,ncy,n_pd", [(1, 5, 4, 2), (7, 12, 8, 3), (64, 40, 20, 10),
-                                            (100, 33, 17, 4), (257, 20, 10, 3), (700, 16, 8, 2)])
+                                            (100, 33, 17, 4), (257, 20, 10, 3), (700, 16, 8, 2), (1024, 8, 4, 2)])
 def test_two_point_wasserstein_vs_oracle(m, ncx, ncy, n_pd):
     """eq:w2: exact assignment per ordered pair of subsampled cells, single-wave
     solver (m <= 256) and four-wave solver (m > 256), against scipy's
@@ -161,3 +161,36 @@ def test_two_point_wasserstein_degenerate_inputs():
     ok = np.ones((9, 9), bool)
     ok[k, :] = ok[:, k] = False
     assert np.all(np.isfinite(got[ok]))
+
+
+def test_two_point_wasserstein_full_scale_properties():
+    """The paper's scale: m = 1000 samples, n_pd = 10, 10^4 ordered cell pairs on a
+    500 x 400 common grid (the four-wave solver, all pairs in one launch).  Too
+    large for the oracle; checked by properties every correct result has: each
+    (k, k') law is the mirror of (k', k) with the same cost matrix, so the two
+    values agree bit for bit; on diagonal pairs the points lie on x = y and the
+    distance is sqrt(2) x the one-point W1 of the cell (vlbm_w1 on sorted
+    samples); every value is finite and non-negative."""
+    m, ncx, ncy, n_pd = 1000, 500, 400, 10
+    g = torch.Generator(device="cuda")
+    g.manual_seed(2605)
+    a = 0.1 + 9.9 * torch.rand((m, ncy * ncx), dtype=torch.float64, device="cuda", generator=g)
+    b = a * (1.0 + 0.3 * (2 * torch.rand((m, ncy * ncx), dtype=torch.float64, device="cuda", generator=g) - 1))
+    P = n_pd ** 4
+    wp = torch.empty(P, dtype=torch.float64, device="cuda")
+    wm = torch.zeros(1, dtype=torch.float64, device="cuda")
+    vlbm.vlbm_w12(a, b, ncx, ncy, m, n_pd, wp, wm)
+    # one-point W1 of the retained cells
+    iy, ix = O.subsample_indices(ncy, n_pd), O.subsample_indices(ncx, n_pd)
+    cells = torch.tensor([j * ncx + i for j in iy for i in ix], device="cuda")
+    sa, sb = a[:, cells].contiguous(), b[:, cells].contiguous()
+    vlbm.vlbm_sort_samples(sa, n_pd * n_pd, m)
+    vlbm.vlbm_sort_samples(sb, n_pd * n_pd, m)
+    w1c = torch.empty(n_pd * n_pd, dtype=torch.float64, device="cuda")
+    vlbm.vlbm_w1(sa, sb, n_pd * n_pd, m, w1c, None)
+    torch.cuda.synchronize()
+    v = wp.cpu().numpy().reshape(n_pd * n_pd, n_pd * n_pd)
+    assert np.all(np.isfinite(v)) and np.all(v >= 0.0)
+    assert np.array_equal(v, v.T)
+    assert np.allclose(np.diag(v), np.sqrt(2.0) * w1c.cpu().numpy(), rtol=1e-12, atol=0)
+    assert wm.item() == pytest.approx(v.mean(), rel=1e-12)
