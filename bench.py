@@ -41,9 +41,14 @@ HBM_PEAK_GBS = 8000.0
 BYTES_PER_LUP = {"fp64": 320.0, "mixed": 224.0}
 
 
+STEP_KERNEL_SOURCES = ("vlbm_step_march.hip", "vlbm_device.h")
+
+
 def kernel_source_hash() -> str:
+    """Hash of the step kernel's sources: a committed traffic measurement is
+    reported only while the kernel it was taken on is unchanged."""
     h = hashlib.sha256()
-    for f in sorted(os.listdir(os.path.join(ROOT, "paper_2605_25282_amd", "csrc"))):
+    for f in STEP_KERNEL_SOURCES:
         with open(os.path.join(ROOT, "paper_2605_25282_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
