@@ -157,6 +157,20 @@ vlbm_status vlbm_init_ensemble(const vlbm_params *p, const vlbm_level *levels, i
 vlbm_status vlbm_set_macroscopic(vlbm_ensemble *e, int32_t level, const double *u);
 
 /*
+ * Checkpoint restore: replace the full state of one level by `state` (DEVICE,
+ * double [4 var][5 slot][n_real][ny][nx], the layout vlbm_get_state writes)
+ * and set each realization's time t[m] and step count steps[m] (HOST arrays
+ * [n_real]; a_last: HOST [n_real] last kinetic speed, or NULL).  The kinetic
+ * speed of the next step is recomputed from the loaded macroscopic state, as
+ * the step that produced it would have recorded it, so stepping on from a
+ * state saved with vlbm_get_state / vlbm_times gives the same bits as never
+ * stopping.  With VLBM_MIXED the FP32 planes store the rounded values.
+ * Synchronizes the stream.
+ */
+vlbm_status vlbm_set_state(vlbm_ensemble *e, int32_t level, const double *state, const double *t,
+                           const int64_t *steps, const double *a_last);
+
+/*
  * Advance every realization of every level by up to n_steps steps of
  * eq:vlbm1-eq:vlbm5, each realization stopping exactly at t_final (the last
  * steps are shortened, taking a = dx/dt).  Realizations already at t_final

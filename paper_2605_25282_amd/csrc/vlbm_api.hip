@@ -28,6 +28,7 @@ template <int PREC> __global__ void step_march_kernel(PhysArgs, MultiLevel, Ctl,
 template <int PREC> __global__ void moments_kernel(PhysArgs, LevelArgs, Ctl, int, double *, double *, double *);
 template <int PREC> __global__ void get_state_kernel(LevelArgs, Ctl, int, double *);
 template <int PREC> __global__ void set_macro_kernel(PhysArgs, LevelArgs, Ctl, const double *);
+template <int PREC> __global__ void set_state_kernel(PhysArgs, LevelArgs, Ctl, const double *);
 template <int PREC>
 __global__ void stats_accumulate_kernel(PhysArgs, LevelArgs, Ctl, int, int, double *, long long, double *, long long);
 __global__ void stats_finalize_kernel(const double *, long long, long long, double *, double *);
@@ -437,34 +438,33 @@ vlbm_status vlbm_init_ensemble(const vlbm_params *p, const vlbm_level *levels, i
     return VLBM_OK;
 }
 
-vlbm_status vlbm_set_macroscopic(vlbm_ensemble *e, int32_t level, const double *u)
+namespace {
+// Re-base the control ring so that slot 0 is current (n_launch = 0), with the
+// realizations of `level` at the given time, step count and last kinetic speed
+// (HOST arrays [R]; NULL = zeros), their status cleared and their wave-speed
+// maximum zeroed for the kernel that loads the state to accumulate.  Other
+// levels keep their clock and buffers (their step counts are kept).
+vlbm_status rebase_ring(vlbm_ensemble *e, int level, const double *t_lvl, const int64_t *steps_lvl,
+                        const double *a_lvl)
 {
-    vlbm_status rc = check_level(e, level);
-    if (rc != VLBM_OK)
-        return rc;
-    if (!u)
-        return fail(VLBM_ERR_ARG, "u is NULL");
-    // Restart the whole ensemble's clock at this level: the other levels keep
-    // their states but the ring is re-based so that slot 0 is current.
     std::vector<double> t, a;
     std::vector<long long> steps;
     std::vector<int> status;
-    if ((rc = read_ctl(e, t, steps, a, status)) != VLBM_OK)
+    vlbm_status rc = read_ctl(e, t, steps, a, status);
+    if (rc != VLBM_OK)
         return rc;
     const LevelArgs &L = e->levels[level];
-    for (int m = 0; m < L.R; ++m) {
-        t[L.ctl_off + m] = 0.0;
-        steps[L.ctl_off + m] = 0;
-        a[L.ctl_off + m] = 0.0;
-        status[L.ctl_off + m] = 0;
-    }
-    std::vector<unsigned long long> amax(e->ctl.nr, 0ull);
     const int nr = e->ctl.nr, ph = phase_of(e);
+    std::vector<unsigned long long> amax(nr, 0ull);
     HIP_TRY(hipMemcpyAsync(amax.data(), e->ctl.amax + (size_t)ph * nr, nr * sizeof(unsigned long long), hipMemcpyDeviceToHost, e->stream));
     HIP_TRY(hipStreamSynchronize(e->stream));
-    for (int m = 0; m < L.R; ++m)
+    for (int m = 0; m < L.R; ++m) {
+        t[L.ctl_off + m] = t_lvl ? t_lvl[m] : 0.0;
+        steps[L.ctl_off + m] = steps_lvl ? (long long)steps_lvl[m] : 0;
+        a[L.ctl_off + m] = a_lvl ? a_lvl[m] : 0.0;
+        status[L.ctl_off + m] = 0;
         amax[L.ctl_off + m] = 0ull;
-    // Other levels: keep their current buffers by keeping their step parity.
+    }
     HIP_TRY(hipMemsetAsync(e->ctl_mem, 0, (size_t)3 * nr * (sizeof(double) * 2 + sizeof(long long) + sizeof(unsigned long long)) + nr * sizeof(int), e->stream));
     HIP_TRY(hipMemcpyAsync(e->ctl.t, t.data(), nr * sizeof(double), hipMemcpyHostToDevice, e->stream));
     HIP_TRY(hipMemcpyAsync(e->ctl.steps, steps.data(), nr * sizeof(long long), hipMemcpyHostToDevice, e->stream));
@@ -472,6 +472,20 @@ vlbm_status vlbm_set_macroscopic(vlbm_ensemble *e, int32_t level, const double *
     HIP_TRY(hipMemcpyAsync(e->ctl.amax, amax.data(), nr * sizeof(unsigned long long), hipMemcpyHostToDevice, e->stream));
     HIP_TRY(hipMemcpyAsync(e->ctl.status, status.data(), nr * sizeof(int), hipMemcpyHostToDevice, e->stream));
     e->n_launch = 0;
+    return VLBM_OK;
+}
+} // namespace
+
+vlbm_status vlbm_set_macroscopic(vlbm_ensemble *e, int32_t level, const double *u)
+{
+    vlbm_status rc = check_level(e, level);
+    if (rc != VLBM_OK)
+        return rc;
+    if (!u)
+        return fail(VLBM_ERR_ARG, "u is NULL");
+    if ((rc = rebase_ring(e, level, nullptr, nullptr, nullptr)) != VLBM_OK)
+        return rc;
+    const LevelArgs &L = e->levels[level];
     const PhysArgs ph_args = phys_args(e->p);
     if (e->p.precision == VLBM_FP64) {
         set_macro_kernel<0><<<node_grid(L), 256, 0, e->stream>>>(ph_args, L, e->ctl, u);
@@ -481,6 +495,33 @@ vlbm_status vlbm_set_macroscopic(vlbm_ensemble *e, int32_t level, const double *
         equilibrium_kernel<1><<<node_grid(L), 256, 0, e->stream>>>(ph_args, L, e->ctl, 0);
     }
     LAUNCH_CHECK("set_macroscopic");
+    HIP_TRY(hipStreamSynchronize(e->stream));
+    return VLBM_OK;
+}
+
+vlbm_status vlbm_set_state(vlbm_ensemble *e, int32_t level, const double *state, const double *t,
+                           const int64_t *steps, const double *a_last)
+{
+    vlbm_status rc = check_level(e, level);
+    if (rc != VLBM_OK)
+        return rc;
+    if (!state || !t || !steps)
+        return fail(VLBM_ERR_ARG, "state, t and steps must be non-NULL");
+    const LevelArgs &L = e->levels[level];
+    for (int m = 0; m < L.R; ++m) {
+        if (!std::isfinite(t[m]) || t[m] < 0.0 || steps[m] < 0)
+            return fail(VLBM_ERR_ARG, "realization %d: t must be finite and >= 0, steps >= 0", m);
+        if (a_last && !(a_last[m] >= 0.0 && std::isfinite(a_last[m])))
+            return fail(VLBM_ERR_ARG, "realization %d: a_last must be finite and >= 0", m);
+    }
+    if ((rc = rebase_ring(e, level, t, steps, a_last)) != VLBM_OK)
+        return rc;
+    const PhysArgs ph_args = phys_args(e->p);
+    if (e->p.precision == VLBM_FP64)
+        set_state_kernel<0><<<node_grid(L), 256, 0, e->stream>>>(ph_args, L, e->ctl, state);
+    else
+        set_state_kernel<1><<<node_grid(L), 256, 0, e->stream>>>(ph_args, L, e->ctl, state);
+    LAUNCH_CHECK("set_state");
     HIP_TRY(hipStreamSynchronize(e->stream));
     return VLBM_OK;
 }

@@ -403,6 +403,41 @@ __global__ void __launch_bounds__(256) set_macro_kernel(PhysArgs ph, LevelArgs L
     block_atomic_max<256>(s, &ctl.amax[L.ctl_off + m]);
 }
 
+// Load a full state (20 values per node, layout [4 var][5 slot][R][ny][nx]) into
+// the buffer each realization's step count selects (slot 0 of the control ring
+// is current), and record the wave-speed maximum of the stored macroscopic
+// state: the kinetic speed of the next step, as the step kernel's epilogue
+// would have recorded it.
+template <int PREC>
+__global__ void __launch_bounds__(256) set_state_kernel(PhysArgs ph, LevelArgs L, Ctl ctl,
+                                                        const double *__restrict__ in)
+{
+    const int i = blockIdx.x * 64 + (threadIdx.x & 63);
+    const int j = blockIdx.y * 4 + (threadIdx.x >> 6);
+    const int m = blockIdx.z;
+    const size_t plane = (size_t)L.nx * L.ny;
+    const long long s = ctl.steps[L.ctl_off + m];
+    auto S = StateOf<PREC>::make(L.buf[s & 1], L.ny, L.nstrip);
+    double w = 0.0;
+    if (i < L.nx && j < L.ny) {
+        const size_t n = (size_t)j * L.nx + i;
+        for (int v = 0; v < 4; ++v)
+            for (int sl = 0; sl < 5; ++sl)
+                S.st(v, sl, m, j, i, in[((size_t)(v * 5 + sl) * L.R + m) * plane + n]);
+        double u[4];
+        for (int v = 0; v < 4; ++v)
+            u[v] = S.ld(v, 0, m, j, i);
+        int bad = 0;
+        w = wave_speed(ph.gamma, u, &bad);
+        const bool fin = isfinite(u[0]) && isfinite(u[1]) && isfinite(u[2]) && isfinite(u[3]);
+        if (!fin)
+            atomicOr(&ctl.status[L.ctl_off + m], STATUS_NONFINITE);
+        else if (bad)
+            atomicOr(&ctl.status[L.ctl_off + m], STATUS_NONPOSITIVE);
+    }
+    block_atomic_max<256>(w, &ctl.amax[L.ctl_off + m]);
+}
+
 // ---------------------------------------------------------------------------
 // Statistics (Sec. 3.2, 3.4)
 // ---------------------------------------------------------------------------
@@ -580,6 +615,8 @@ template __global__ void get_state_kernel<0>(LevelArgs, Ctl, int, double *);
 template __global__ void get_state_kernel<1>(LevelArgs, Ctl, int, double *);
 template __global__ void set_macro_kernel<0>(PhysArgs, LevelArgs, Ctl, const double *);
 template __global__ void set_macro_kernel<1>(PhysArgs, LevelArgs, Ctl, const double *);
+template __global__ void set_state_kernel<0>(PhysArgs, LevelArgs, Ctl, const double *);
+template __global__ void set_state_kernel<1>(PhysArgs, LevelArgs, Ctl, const double *);
 template __global__ void stats_accumulate_kernel<0>(PhysArgs, LevelArgs, Ctl, int, int, double *, long long, double *, long long);
 template __global__ void stats_accumulate_kernel<1>(PhysArgs, LevelArgs, Ctl, int, int, double *, long long, double *, long long);
 template __global__ void sort_samples_kernel<1>(double *, long long, int, int);

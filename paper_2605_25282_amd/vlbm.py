@@ -87,6 +87,7 @@ def lib():
             "vlbm_init_ensemble": ([P, ctypes.POINTER(Level), i32, _DP, i32, _VP,
                                     ctypes.POINTER(_VP)], i32),
             "vlbm_set_macroscopic": ([_VP, i32, _VP], i32),
+            "vlbm_set_state": ([_VP, i32, _VP, _DP, ctypes.POINTER(i64), _DP], i32),
             "vlbm_step": ([_VP, dbl, i32, ctypes.POINTER(i32)], i32),
             "vlbm_times": ([_VP, i32, _DP, ctypes.POINTER(i64), _DP, ctypes.POINTER(i32)], i32),
             "vlbm_get_state": ([_VP, i32, _VP], i32),
@@ -154,6 +155,15 @@ def vlbm_init_ensemble(p: Params, levels: list[Level], coeffs: np.ndarray | None
 
 def vlbm_set_macroscopic(h, level: int, u) -> None:
     _check(lib().vlbm_set_macroscopic(h, level, _ptr(u)))
+
+
+def vlbm_set_state(h, level: int, state, t, steps, a_last=None) -> None:
+    tt = np.ascontiguousarray(t, dtype=np.float64)
+    ss = np.ascontiguousarray(steps, dtype=np.int64)
+    aa = None if a_last is None else np.ascontiguousarray(a_last, dtype=np.float64)
+    _check(lib().vlbm_set_state(h, level, _ptr(state), tt.ctypes.data_as(_DP),
+                                ss.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                None if aa is None else aa.ctypes.data_as(_DP)))
 
 
 def vlbm_step(h, t_final: float, n_steps: int, want_done: bool = True):
@@ -319,6 +329,9 @@ class Ensemble:
 
     def set_macroscopic(self, level: int, u) -> None:
         vlbm_set_macroscopic(self.h, level, u)
+
+    def set_state(self, level: int, state, t, steps, a_last=None) -> None:
+        vlbm_set_state(self.h, level, state, t, steps, a_last)
 
     def moments(self, level: int = 0):
         import torch

@@ -97,6 +97,7 @@ def test_init_rejects_before_any_device_work(lib):
 
 def test_null_handles_rejected(lib):
     assert lib.vlbm_step(None, 1.0, 1, None) == vlbm.ERR_ARG
+    assert lib.vlbm_set_state(None, 0, None, None, None, None) == vlbm.ERR_ARG
     assert lib.vlbm_moments(None, 0, None, None, None) == vlbm.ERR_ARG
     assert lib.vlbm_ensemble_stats(None, 0, 1, None, 0, None, 0) == vlbm.ERR_ARG
     assert lib.vlbm_sort_samples(None, 1, 1, None) == vlbm.ERR_ARG

@@ -508,3 +508,35 @@ def test_mixed_vs_fp64_statistics_gpu():
     ew = w1m.item() / m64[0].mean()
     print(f"mixed vs fp64: mean {em:.3e}, std {es:.3e}, W1/mean(rho) {ew:.3e}")
     assert em < 1e-3 and es < 1e-3 and ew < 1e-3
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_checkpoint_resume_is_bitwise(precision):
+    """Save every level's state and clock after 33 steps (vlbm_get_state,
+    vlbm_times), restore them into a fresh ensemble (vlbm_set_state) and step
+    on: after 70 steps in all, states, times and step counts equal those of an
+    uninterrupted run bit for bit (two levels, one launch per step, graph
+    replays on both sides)."""
+    R = 5
+    levels = _three_levels(48)[:2]
+    coefs = inputs.kl_coefficients(inputs.DEFAULT_SEED, 3, R)
+    prm = vlbm.Params.jet(precision=precision)
+    ref = vlbm.Ensemble(prm, levels, coefs, R)
+    ref.step(1e30, 70)
+    want = [(ref.state(l).cpu().numpy(), ref.times(l)) for l in range(2)]
+    ref.close()
+    a = vlbm.Ensemble(prm, levels, coefs, R)
+    a.step(1e30, 33)
+    saved = [(a.state(l), a.times(l)) for l in range(2)]
+    a.close()
+    b = vlbm.Ensemble(prm, levels, np.zeros_like(coefs), R)  # a different initial datum
+    for l, (st, (t, s, al, status)) in enumerate(saved):
+        assert np.all(s == 33) and np.all(status == 0)
+        b.set_state(l, st, t, s, al)
+    b.step(1e30, 37)
+    for l in range(2):
+        got = b.state(l).cpu().numpy()
+        assert np.array_equal(got, want[l][0]), l
+        for x, y in zip(b.times(l)[:3], want[l][1][:3]):
+            assert np.array_equal(x, y)
+    b.close()
