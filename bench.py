@@ -93,6 +93,11 @@ def cpu_baseline(workload, seconds_target: float = 15.0):
                       f"jet on {threads} host threads ({el:.1f} s, {lups:.3e} node updates)"}
 
 
+def progress(msg: str) -> None:
+    """One line per finished stage on stderr (stdout carries only the JSON line)."""
+    print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -117,6 +122,12 @@ def main() -> int:
                     help="paper: the paper's domain [0,2.5]x[-1,1] with grids 500x400, 1000x800, "
                          "2000x1600 and the study at t = 0.0005 k, k = 1..7")
     ap.add_argument("--study-m", type=int, default=0, help="realizations (0: 128 config, 32 paper)")
+    ap.add_argument("--c5", action="store_true",
+                    help="instead of the default line: the largest level (5056x2528) with its "
+                         "2528x1264 partner on the same seeds, streamed in batches to t=1e-3 with "
+                         "running mean/std and sample stores, then the one-point W1 between the levels")
+    ap.add_argument("--c5-batches", type=int, default=2)
+    ap.add_argument("--c5-batch-m", type=int, default=16)
     ap.add_argument("--profile-launches", type=int, default=0,
                     help="profiling mode: initial datum, this many step launches and a "
                          "2 GiB device copy, no statistics and no JSON line")
@@ -151,6 +162,8 @@ def main() -> int:
 
     if args.study:
         return run_study(args, torch, vlbm, inputs)
+    if args.c5:
+        return run_c5(args, torch, vlbm, inputs)
 
     if args.profile_launches > 0:
         params = vlbm.Params.jet(precision=args.precision if args.precision != "both" else "fp64")
@@ -187,6 +200,7 @@ def main() -> int:
             h = vlbm.vlbm_init_ensemble(params, [level], coefs, R, stream)
             tuned = vlbm.vlbm_autotune(h, w.t_final, 4, 1)
             vlbm.vlbm_destroy(h)
+            progress(f"{precision}: autotuned {tuned[0]} rows per wave")
         n_timed = args.steps if timed_steps is None else timed_steps
         n_warm = args.warmup if warmup is None else warmup
         step_ms, step_launches, totals = [0.0], [0], {"lups": 0.0}
@@ -224,10 +238,12 @@ def main() -> int:
 
         for k in range(n_warm):
             one_step(k, False)
+            progress(f"{precision}: warmup pass {k + 1}/{n_warm} done")
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for k in range(n_timed):
             one_step(n_warm + k, True)
+            progress(f"{precision}: timed pass {k + 1}/{n_timed} done")
         torch.cuda.synchronize()
         elapsed = time.perf_counter() - t0
         steps_r = last["steps"]
@@ -411,6 +427,90 @@ def run_study(args, torch, vlbm, inputs) -> int:
                             for p, v in (("cauchy", convergence.cauchy_pairs(len(shapes) - 1)),
                                          ("reference", convergence.reference_pairs(len(shapes) - 1)))},
                   "checkpoints": rows},
+    }
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+def run_c5(args, torch, vlbm, inputs) -> int:
+    """The largest level of the study and its half-resolution partner in one
+    ensemble per batch (same seeds on both levels), batches streamed through
+    HBM: the running statistics merge each batch (vlbm_ensemble_stats with
+    n_prev / m_offset); after the last batch the sample stores are sorted and
+    the one-point W1 between the levels is taken on the 2528 x 1264 grid."""
+    import numpy as np
+
+    precision = args.precision if args.precision != "both" else "fp64"
+    fine = inputs.WORKLOADS["jet5056"]
+    coarse = inputs.JetWorkload("jet2528", fine.nx // 2, fine.ny // 2, fine.m, fine.t_final)
+    works = [coarse, fine]
+    levels = [(w.nx, w.ny, w.dx, w.y_min) for w in works]
+    B, Mb = args.c5_batches, args.c5_batch_m
+    M = B * Mb
+    ncx, ncy = coarse.nx, coarse.ny
+    ncell = ncx * ncy
+    params = vlbm.Params.jet(precision=precision)
+    stream = torch.cuda.current_stream()
+    dev = dict(dtype=torch.float64, device="cuda")
+    acc = [torch.empty((3, 2, ncell), **dev) for _ in works]
+    smp = [torch.empty((M, ncell), **dev) for _ in works]
+    step_s, lups, launches, tuned = 0.0, 0.0, 0, None
+    t0 = time.perf_counter()
+    for b in range(B):
+        coefs = inputs.kl_coefficients(inputs.DEFAULT_SEED, b * Mb, Mb)
+        ens = vlbm.Ensemble(params, levels, coefs, Mb)
+        if b == 0 and not args.no_tune:
+            tuned = ens.autotune(fine.t_final, 4)  # live steps, cached for later batches
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        done, last = False, time.perf_counter()
+        while not done:
+            done = ens.step(fine.t_final, args.chunk)
+            launches += args.chunk
+            if time.perf_counter() - last > 30:
+                progress(f"batch {b + 1}/{B}: stepping, level steps {ens.times(1)[1].min()}")
+                last = time.perf_counter()
+        e1.record(stream)
+        e1.synchronize()
+        step_s += e0.elapsed_time(e1) / 1e3
+        for l, w in enumerate(works):
+            t, s, a, status = ens.times(l)
+            if np.any(status != 0) or np.any(t != w.t_final):
+                print(json.dumps({"error": f"batch {b}, level {l} did not reach t_final cleanly"}))
+                return 1
+            lups += float(s.sum()) * w.nx * w.ny
+            vlbm.vlbm_ensemble_stats(ens.h, l, w.nx // ncx, acc[l], b * Mb, smp[l], b * Mb)
+        ens.close()
+        progress(f"batch {b + 1}/{B} done ({step_s:.1f} s of stepping so far)")
+    mean = [torch.empty((3, ncell), **dev) for _ in works]
+    std = [torch.empty((3, ncell), **dev) for _ in works]
+    for l in range(2):
+        vlbm.vlbm_stats_finalize(acc[l], ncell, M, mean[l], std[l], stream)
+        vlbm.vlbm_sort_samples(smp[l], ncell, M, stream)
+    w1c = torch.empty(ncell, **dev)
+    w1m = torch.zeros(1, **dev)
+    vlbm.vlbm_w1(smp[0], smp[1], ncell, M, w1c, w1m, stream)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    bpl = BYTES_PER_LUP[precision]
+    out = {
+        "metric": METRIC, "value": round(lups / elapsed / 1e9, 4), "unit": "GLUPS", "n_gpus": 1,
+        "steps": 1, "warmup": 0, "ms_per_step": round(elapsed * 1e3, 3), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64" if precision == "fp64" else "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": f"largest level 5056x2528 with 2528x1264 on the same seeds, {B} batches of "
+                               f"{Mb} realizations streamed to t={fine.t_final:g} (the study's M = 1000 "
+                               f"would be {1000 // Mb} such batches), {precision}",
+                   "launches": launches, "step_kernel_rows_per_wave": tuned,
+                   "extrapolated_s_for_m1000": round(elapsed / M * 1000, 1)},
+        "roofline": {"bound": "hbm", "achieved": round(bpl * lups / step_s / 1e9, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(bpl * lups / step_s / 1e9 / HBM_PEAK_GBS, 4),
+                     "traffic": None, "kernel": "vlbm step kernel (both levels per launch)",
+                     "bytes_per_node_update": bpl},
+        "statistics": {"w1_between_levels_mean": w1m.item(),
+                       "mean_rho_domain_average": [float(m[0].mean().item()) for m in mean],
+                       "std_rho_domain_average": [float(s[0].mean().item()) for s in std]},
     }
     print(json.dumps(out), flush=True)
     return 0
