@@ -54,10 +54,11 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(precision: str):
+def measured_traffic(precision: str, workload: str):
     """HBM bytes per launch of the step kernel from the committed rocprofv3
-    counter summary, if it was taken on the current kernel sources."""
-    path = os.path.join(ROOT, "profiles", f"traffic_step_jet640_{precision}.json")
+    counter summary of this workload, if it was taken on the current kernel
+    sources (null for a workload without one)."""
+    path = os.path.join(ROOT, "profiles", f"traffic_step_{workload}_{precision}.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
@@ -301,7 +302,7 @@ def main() -> int:
                    "step_kernel_rows_per_wave": r0["tuned_rows"]},
         "roofline": {"bound": "hbm", "achieved": round(r0["achieved"], 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(r0["achieved"] / HBM_PEAK_GBS, 4),
-                     "traffic": measured_traffic(head),
+                     "traffic": measured_traffic(head, w.name),
                      "kernel": "vlbm step kernel", "bytes_per_node_update": BYTES_PER_LUP[head],
                      "avg_launch_ms": round(r0["avg_launch_ms"], 5),
                      "launches_per_pass": r0["launches_per_pass"],
@@ -332,7 +333,7 @@ def main() -> int:
             "speedup_vs_fp64": round(rm["value"] / r0["value"], 4),
             "roofline": {"bound": "hbm", "achieved": round(rm["achieved"], 1), "peak": HBM_PEAK_GBS,
                          "unit": "GB/s", "frac": round(rm["achieved"] / HBM_PEAK_GBS, 4),
-                         "traffic": measured_traffic("mixed"),
+                         "traffic": measured_traffic("mixed", w.name),
                          "bytes_per_node_update": BYTES_PER_LUP["mixed"],
                          "avg_launch_ms": round(rm["avg_launch_ms"], 5),
                          "frac_of_device_copy": round(rm["achieved"] / copy_gbs, 4)},
@@ -482,6 +483,7 @@ def run_c5(args, torch, vlbm, inputs) -> int:
             lups += float(s.sum()) * w.nx * w.ny
             vlbm.vlbm_ensemble_stats(ens.h, l, w.nx // ncx, acc[l], b * Mb, smp[l], b * Mb)
         ens.close()
+        del ens  # release this batch's state before the next batch allocates its own
         progress(f"batch {b + 1}/{B} done ({step_s:.1f} s of stepping so far)")
     mean = [torch.empty((3, ncell), **dev) for _ in works]
     std = [torch.empty((3, ncell), **dev) for _ in works]
