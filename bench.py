@@ -455,6 +455,9 @@ def run_c5(args, torch, vlbm, inputs) -> int:
     dev = dict(dtype=torch.float64, device="cuda")
     acc = [torch.empty((3, 2, ncell), **dev) for _ in works]
     smp = [torch.empty((M, ncell), **dev) for _ in works]
+    # the fine level's statistics on its own nodes too (no restriction): the
+    # share of the ensemble variance that sits at the grid scale
+    acc_nodes = torch.empty((3, 2, fine.nx * fine.ny), **dev)
     step_s, lups, launches, tuned = 0.0, 0.0, 0, None
     t0 = time.perf_counter()
     for b in range(B):
@@ -482,6 +485,7 @@ def run_c5(args, torch, vlbm, inputs) -> int:
                 return 1
             lups += float(s.sum()) * w.nx * w.ny
             vlbm.vlbm_ensemble_stats(ens.h, l, w.nx // ncx, acc[l], b * Mb, smp[l], b * Mb)
+        vlbm.vlbm_ensemble_stats(ens.h, 1, 1, acc_nodes, b * Mb, None, 0)
         ens.close()
         del ens  # release this batch's state before the next batch allocates its own
         progress(f"batch {b + 1}/{B} done ({step_s:.1f} s of stepping so far)")
@@ -490,6 +494,8 @@ def run_c5(args, torch, vlbm, inputs) -> int:
     for l in range(2):
         vlbm.vlbm_stats_finalize(acc[l], ncell, M, mean[l], std[l], stream)
         vlbm.vlbm_sort_samples(smp[l], ncell, M, stream)
+    std_nodes = torch.empty((3, fine.nx * fine.ny), **dev)
+    vlbm.vlbm_stats_finalize(acc_nodes, fine.nx * fine.ny, M, None, std_nodes, stream)
     w1c = torch.empty(ncell, **dev)
     w1m = torch.zeros(1, **dev)
     vlbm.vlbm_w1(smp[0], smp[1], ncell, M, w1c, w1m, stream)
@@ -512,7 +518,8 @@ def run_c5(args, torch, vlbm, inputs) -> int:
                      "bytes_per_node_update": bpl},
         "statistics": {"w1_between_levels_mean": w1m.item(),
                        "mean_rho_domain_average": [float(m[0].mean().item()) for m in mean],
-                       "std_rho_domain_average": [float(s[0].mean().item()) for s in std]},
+                       "std_rho_domain_average": [float(s[0].mean().item()) for s in std],
+                       "std_rho_domain_average_fine_level_own_nodes": float(std_nodes[0].mean().item())},
     }
     print(json.dumps(out), flush=True)
     return 0
