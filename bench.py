@@ -324,13 +324,44 @@ def main() -> int:
         w1m = torch.zeros(1, dtype=torch.float64, device="cuda")
         vlbm.vlbm_w1(a["sorted"], b["sorted"], ncell_w1, R, w1c, w1m, stream)
         torch.cuda.synchronize()
-        return {"mean_rel_l1": [round(rel(b["mean"][f], a["mean"][f]), 9) for f in range(3)],
-                "std_rel_l1": [round(rel(b["std"][f], a["std"][f]), 9) for f in range(3)],
-                "w1_over_mean_rho": round(float(w1m.item()) / float(a["mean"][0].mean()), 9),
+        sig = lambda x: float(f"{x:.4g}")
+        return {"mean_rel_l1": [sig(rel(b["mean"][f], a["mean"][f])) for f in range(3)],
+                "std_rel_l1": [sig(rel(b["std"][f], a["std"][f])) for f in range(3)],
+                "w1_over_mean_rho": sig(float(w1m.item()) / float(a["mean"][0].mean())),
                 "fields": ["rho", "|v|", "p"]}
+
+    def early_stats(precision: str, t_early: float, first_seed: int = 0):
+        """Ensemble statistics of a fresh run to t_early (untimed)."""
+        params = vlbm.Params.jet(precision=precision)
+        level, bufs = make_level(params)
+        cf = inputs.kl_coefficients(inputs.DEFAULT_SEED, first_seed, R)
+        h = vlbm.vlbm_init_ensemble(params, [level], cf, R, stream)
+        while not vlbm.vlbm_step(h, t_early, args.chunk, want_done=True):
+            pass
+        acc = torch.empty((3, 2, ncell), dtype=torch.float64, device="cuda")
+        mean = torch.empty((3, ncell), dtype=torch.float64, device="cuda")
+        std = torch.empty_like(mean)
+        sacc = torch.empty((3, 2, ncell_w1), dtype=torch.float64, device="cuda")
+        smp = torch.empty((R, ncell_w1), dtype=torch.float64, device="cuda")
+        vlbm.vlbm_ensemble_stats(h, 0, r_stats, acc, 0, None, 0)
+        vlbm.vlbm_stats_finalize(acc, ncell, R, mean, std, stream)
+        vlbm.vlbm_ensemble_stats(h, 0, r_w1, sacc, 0, smp, 0)
+        vlbm.vlbm_sort_samples(smp, ncell_w1, R, stream)
+        vlbm.vlbm_destroy(h)
+        return {"mean": mean, "std": std, "sorted": smp}
 
     if "mixed" in res and head == "fp64":
         rm = res["mixed"]
+        # the same comparison at earlier times, next to two FP64 ensembles on
+        # disjoint seeds: while the mixed run's difference stays below the
+        # latter the realizations have not yet decorrelated pathwise
+        early = []
+        for frac in (0.01, 0.1):
+            t_e = w.t_final * frac
+            ref = early_stats("fp64", t_e)
+            early.append({"t": t_e, "mixed_vs_fp64": stat_errors(ref, early_stats("mixed", t_e)),
+                          "fp64_independent": stat_errors(ref, early_stats("fp64", t_e, first_seed=R))})
+            progress(f"early comparison at t={t_e:g} done")
         # sampling-noise scale: an independent FP64 ensemble (the next R seeds)
         other = run_variant("fp64", first_seed=R, timed_steps=0, warmup=1, tune=False)
         out["mixed"] = {
@@ -345,6 +376,7 @@ def main() -> int:
                          "frac_of_device_copy": round(rm["achieved"] / copy_gbs, 4)},
             "error_vs_fp64": stat_errors(res["fp64"], rm),
             "fp64_independent_ensemble_difference": stat_errors(res["fp64"], other),
+            "error_vs_fp64_earlier_times": early,
             "time_steps_per_realization": rm["steps"],
             "step_kernel_rows_per_wave": rm["tuned_rows"],
         }
