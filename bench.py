@@ -76,7 +76,8 @@ def cpu_baseline(workload, seconds_target: float = 15.0):
     import oracle as O
     from paper_2605_25282_amd import inputs
 
-    threads = min(8, os.cpu_count() or 1)
+    # the host share of one GPU: OMP_NUM_THREADS where the machine sets it
+    threads = min(int(os.environ.get("OMP_NUM_THREADS", "8") or 8), os.cpu_count() or 1, 16)
     p = O.Params()
     g = O.Grid(workload.nx, workload.ny, workload.dx, workload.y_min)
     coefs = inputs.kl_coefficients(inputs.DEFAULT_SEED, 0, threads)
@@ -89,7 +90,17 @@ def cpu_baseline(workload, seconds_target: float = 15.0):
     states, t, n, status = O.run_ensemble(p, g, coefs, 1e30, max_steps=steps, threads=threads)
     el = time.perf_counter() - t0
     lups = float(n.sum()) * workload.nx * workload.ny
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
     return {"value": lups / el / 1e9, "unit": "GLUPS", "cores": threads, "kind": "oracle",
+            "cpu_model": model, "host_cpus": os.cpu_count(),
             "sample": f"{threads} realizations x {steps} steps of the {workload.nx}x{workload.ny} "
                       f"jet on {threads} host threads ({el:.1f} s, {lups:.3e} node updates)"}
 
@@ -211,12 +222,18 @@ def main() -> int:
         n_timed = args.steps if timed_steps is None else timed_steps
         n_warm = args.warmup if warmup is None else warmup
         step_ms, step_launches, totals = [0.0], [0], {"lups": 0.0}
+        phases = {"init": 0.0, "step": 0.0, "stats": 0.0}
         last = {}
 
         def one_step(k: int, timed: bool):
+            # phases timed on the host: each ends with a synchronization
+            # (initialisation and vlbm_destroy synchronize the stream, the last
+            # vlbm_step reads the completion flag back)
+            c0 = time.perf_counter()
             h = vlbm.vlbm_init_ensemble(params, [level], coefs, R, stream)
             if args.chunk_rows:
                 vlbm.vlbm_tune(h, "march", args.chunk_rows)
+            c1 = time.perf_counter()
             done = False
             while not done:
                 if timed:
@@ -229,6 +246,7 @@ def main() -> int:
                     e1.synchronize()
                     step_ms[0] += e0.elapsed_time(e1)
                     step_launches[0] += args.chunk
+            c2 = time.perf_counter()
             t, s, a, status = vlbm.vlbm_times(h, 0, R)
             vlbm.vlbm_ensemble_stats(h, 0, r_stats, acc, 0, None, 0)
             vlbm.vlbm_stats_finalize(acc, ncell, R, mean, std, stream)
@@ -238,8 +256,11 @@ def main() -> int:
             if k > 0:
                 vlbm.vlbm_w1(cur, prev, ncell_w1, R, w1c, w1m, stream)
             vlbm.vlbm_destroy(h)
+            c3 = time.perf_counter()
             if timed:
                 totals["lups"] += float(s.sum()) * w.nx * w.ny
+                for key, dt in (("init", c1 - c0), ("step", c2 - c1), ("stats", c3 - c2)):
+                    phases[key] += dt
             last["steps"], last["sorted"] = s, cur
             return s
 
@@ -266,6 +287,7 @@ def main() -> int:
             "tuned_rows": tuned[0],
             "steps": [int(steps_r.min()), int(steps_r.max())],
             "w1_rerun": float(w1m.item()) if n_warm + n_timed > 1 else None,
+            "phases_ms": {key: round(v * 1e3 / max(n_timed, 1), 3) for key, v in phases.items()},
             "mean": mean.clone(), "std": std.clone(), "sorted": last["sorted"].clone(),
         }
 
@@ -305,7 +327,8 @@ def main() -> int:
                    "precision": head, "nx": w.nx, "ny": w.ny, "realizations": R,
                    "t_final": w.t_final, "seed": inputs.DEFAULT_SEED,
                    "time_steps_per_realization": r0["steps"],
-                   "step_kernel_rows_per_wave": r0["tuned_rows"]},
+                   "step_kernel_rows_per_wave": r0["tuned_rows"],
+                   "phases_ms_per_step": r0["phases_ms"]},
         "roofline": {"bound": "hbm", "achieved": round(r0["achieved"], 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(r0["achieved"] / HBM_PEAK_GBS, 4),
                      "traffic": measured_traffic(head, w.name),
@@ -379,6 +402,7 @@ def main() -> int:
             "error_vs_fp64_earlier_times": early,
             "time_steps_per_realization": rm["steps"],
             "step_kernel_rows_per_wave": rm["tuned_rows"],
+            "phases_ms_per_step": rm["phases_ms"],
         }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w)
