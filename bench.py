@@ -134,6 +134,8 @@ def main() -> int:
                     help="paper: the paper's domain [0,2.5]x[-1,1] with grids 500x400, 1000x800, "
                          "2000x1600 and the study at t = 0.0005 k, k = 1..7")
     ap.add_argument("--study-m", type=int, default=0, help="realizations (0: 128 config, 32 paper)")
+    ap.add_argument("--study-levels", type=int, default=3, choices=[3, 4],
+                    help="paper geometry: 4 adds the 4000x3200 level (the paper's full hierarchy)")
     ap.add_argument("--c5", action="store_true",
                     help="instead of the default line: the largest level (5056x2528) with its "
                          "2528x1264 partner on the same seeds, streamed in batches to t=1e-3 with "
@@ -420,7 +422,7 @@ def run_study(args, torch, vlbm, inputs) -> int:
 
     precision = args.precision if args.precision != "both" else "fp64"
     if args.study_geometry == "paper":
-        works = [inputs.PAPER_GRIDS[f"paper{nx}"] for nx in (500, 1000, 2000)]
+        works = [inputs.PAPER_GRIDS[f"paper{nx}"] for nx in (500, 1000, 2000, 4000)[:args.study_levels]]
         R = args.study_m or 32
         checkpoints = list(inputs.PAPER_CHECKPOINTS)
         geometry = "the paper's domain [0,2.5]x[-1,1]"
@@ -440,6 +442,7 @@ def run_study(args, torch, vlbm, inputs) -> int:
         ens = vlbm.Ensemble(params, levels, coefs, R)
         tuned = ens.autotune(checkpoints[0], 4)
         ens.close()
+        del ens  # release the tuning ensemble's state before the measured one allocates its own
     ens = vlbm.Ensemble(params, levels, coefs, R)
     if args.chunk_rows:
         ens.tune("march", args.chunk_rows)
@@ -465,6 +468,7 @@ def run_study(args, torch, vlbm, inputs) -> int:
             prev[l] = s
             steps.append([int(s.min()), int(s.max())])
         st = convergence.study(ens, dx, 10, stream)
+        progress(f"study: checkpoint t={tc:g} done ({launches} launches)")
         rows.append({"t": tc, "time_steps_per_realization": steps,
                      "errors": {f"{p}/{o}": [float(f"{x:.6g}") for x in v] for (p, o), v in st.errors.items()},
                      "rates": {f"{p}/{o}": round(v, 4) for (p, o), v in st.rates.items()}})
