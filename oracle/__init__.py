@@ -66,7 +66,11 @@ class _Grid(ctypes.Structure):
 class Params:
     """Physical and numerical parameters (Sec. 2.1-2.3 of the paper)."""
     gamma: float = 5.0 / 3.0
-    alpha: float = 0.0
+    # weight of the rest population M_5 = alpha u (eq:maxwellians5; the paper
+    # leaves it free): the standard D2Q5 weights, 1/3 at rest and 1/6 per
+    # moving direction.  With alpha = 0 every update draws on the four
+    # neighbours only and the even and odd sublattices decouple.
+    alpha: float = 1.0 / 3.0
     kappa: float = 1.0
     rlmp_relax: float = 0.1
     pos_eps: float = 1e-2

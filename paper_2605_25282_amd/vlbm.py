@@ -44,7 +44,7 @@ class Params(ctypes.Structure):
 
     @classmethod
     def jet(cls, **kw) -> "Params":
-        d = dict(gamma=5.0 / 3.0, alpha=0.0, kappa=1.0, rlmp_relax=0.1, pos_eps=1e-2,
+        d = dict(gamma=5.0 / 3.0, alpha=1.0 / 3.0, kappa=1.0, rlmp_relax=0.1, pos_eps=1e-2,
                  rho_amb=0.5, p_amb=0.4127, rho_jet=5.0, v_jet=800.0, r_jet=0.05, kl_amp=0.1,
                  kl_modes=10, kl_decay=2, bc="jet", limiter="limiter", precision="fp64")
         d.update(kw)

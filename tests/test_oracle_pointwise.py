@@ -113,16 +113,18 @@ def test_kinetic_speed_is_bouchut_bound(alpha):
         assert min_eig(0.98 * a) < -1e-3
 
 
-def test_kinetic_speed_max_over_all_nodes():
-    """a_n uses the fastest node of the whole grid, boundary layers included."""
-    p = O.Params(kappa=1.3)
+@pytest.mark.parametrize("alpha", [0.0, 1.0 / 3.0, 0.5])
+def test_kinetic_speed_max_over_all_nodes(alpha):
+    """a_n uses the fastest node of the whole grid, boundary layers included,
+    with the factor 2 / (1 - alpha) of the Bouchut bound."""
+    p = O.Params(kappa=1.3, alpha=alpha)
     g = O.Grid(6, 5, 0.01)
     st = np.zeros((20, 5, 6))
     st[0:4] = _state(1.0, 0.1, 0.0, 1.0, p.gamma)[:, None, None]
     st[0:4, 4, 5] = _state(0.2, -9.0, 1.0, 0.5, p.gamma)  # corner copy-layer node
     s_corner, bad = O.wave_speed(p, st[0:4, 4, 5])
     assert not bad
-    assert O.kinetic_speed(p, g, st) == pytest.approx(1.3 * 2.0 * s_corner, rel=1e-15)
+    assert O.kinetic_speed(p, g, st) == pytest.approx(1.3 * 2.0 * s_corner / (1.0 - alpha), rel=1e-15)
     assert s_corner == pytest.approx(9.0 + math.sqrt(p.gamma * 0.5 / 0.2), rel=1e-14)
 
 

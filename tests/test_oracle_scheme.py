@@ -81,7 +81,7 @@ def test_periodic_conservation(alpha, theta):
 def test_theta_zero_is_lax_friedrichs():
     """theta = 0, alpha = 0: eq:vlbm5 reduces to the classical Lax-Friedrichs scheme
     u^{n+1} = mean of the 4 neighbours - dt/(2dx) (centred flux differences), dt = dx/a."""
-    p = O.Params(bc="periodic", gamma=1.4, theta_mode="zero")
+    p = O.Params(bc="periodic", gamma=1.4, theta_mode="zero", alpha=0.0)  # the reduction needs alpha = 0
     g = O.Grid(10, 9, 0.1)
     st = _nonequilibrium_state(p, g, _smooth_state(g, 6, p.gamma), 7)
     u = st[0:4]
@@ -295,3 +295,45 @@ def test_mixed_storage_statistics_close_to_fp64():
         assert np.abs(mb - ma).sum() / np.abs(ma).sum() < 1e-3
         assert np.abs(sb - sa).sum() / np.abs(sa).sum() < 1e-3
     assert O.w1(res["fp64"][0], res["mixed"][0]).mean() / O.ensemble_mean(res["fp64"][0]).mean() < 1e-3
+
+
+def _checkerboard(p, n=16, eps=1e-3):
+    g = O.Grid(n, n, 1.0 / n, -0.5)
+    u = np.zeros((4, n, n))
+    for j in range(n):
+        for i in range(n):
+            rho = 1.0 + eps * (-1.0) ** (i + j)
+            v1, pr = 0.3, 1.0
+            u[:, j, i] = [rho, rho * v1, 0.0, pr / (p.gamma - 1.0) + 0.5 * rho * v1 * v1]
+    sign = np.array([[(-1.0) ** (i + j) for i in range(n)] for j in range(n)])
+    return g, O.from_macroscopic(p, g, u), sign
+
+
+@pytest.mark.parametrize("alpha", [0.1, 1.0 / 3.0, 0.5, 0.75])
+def test_checkerboard_factor_with_theta_zero(alpha):
+    """eq:vlbm5 with theta = 0 gives each node alpha of its own state and, summed
+    over M_1..M_4 of its four neighbours, 1 - alpha of theirs (the flux terms of
+    opposite neighbours cancel on a checkerboard): a density checkerboard on a
+    uniform flow is multiplied by exactly 2 alpha - 1 per step."""
+    p = O.Params(bc="periodic", gamma=1.4, alpha=alpha, kl_modes=0, theta_mode="zero")
+    g, st, sign = _checkerboard(p)
+    amp0 = (st[0] * sign).mean()
+    for n in (1, 2, 5):
+        s2, _, steps, _, rc = O.run(p, g, st, 1e30, max_steps=n)
+        assert rc == O.OK and steps == n
+        assert (s2[0] * sign).mean() == pytest.approx(amp0 * (2 * alpha - 1) ** n, rel=1e-9, abs=1e-15)
+
+
+@pytest.mark.parametrize("mode", ["limiter", "zero", "one"])
+def test_checkerboard_is_neutral_without_rest_population(mode):
+    """With alpha = 0 a node's update draws on its four neighbours only, so the
+    even and odd sublattices decouple: the checkerboard keeps its amplitude
+    (sign alternating every step) for every theta.  This mode is what alpha > 0
+    damps, and the reason the jet runs use alpha = 1/3."""
+    p = O.Params(bc="periodic", gamma=1.4, alpha=0.0, kl_modes=0, theta_mode=mode)
+    g, st, sign = _checkerboard(p)
+    amp0 = (st[0] * sign).mean()
+    for n in (1, 2, 11, 40):
+        s2, _, steps, _, rc = O.run(p, g, st, 1e30, max_steps=n)
+        assert rc == O.OK
+        assert (s2[0] * sign).mean() == pytest.approx(amp0 * (-1.0) ** n, rel=1e-9)
