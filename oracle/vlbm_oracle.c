@@ -157,9 +157,9 @@ double orc_wave_speed(const orc_params *P, const double *u, int *bad)
 
 /* Correctly rounded cosine and sine of a double: evaluated in binary128 and
  * rounded once to binary64.  The inlet profile feeds a scheme that amplifies
- * one-ulp differences (one ulp at one inlet node becomes a 2.7e-11 relative
- * difference of the state within 50 steps of the Mach-2000 jet, beyond a
- * 1e-11 comparison), so it is defined with correctly rounded elementary
+ * one-ulp differences (one ulp in one inlet density grows to a 1e-12 .. 6e-11
+ * relative difference of the state within 50 steps of the Mach-2000 jet,
+ * depending on alpha), so it is defined with correctly rounded elementary
  * functions rather than with whatever accuracy a particular libm offers. */
 static double cr_cos(double x) { return (double)cosq((__float128)x); }
 static double cr_sin(double x) { return (double)sinq((__float128)x); }
