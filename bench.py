@@ -146,6 +146,11 @@ def main() -> int:
                     help="instead of the default line: time the two-point W_{1,2} at the paper's "
                          "scale (1000 samples, 10 x 10 subsampled cells, 10^4 exact assignments) on "
                          "seeded synthetic samples of a 500 x 400 common grid")
+    ap.add_argument("--centerline", type=int, default=0, metavar="NX",
+                    help="instead of the default line: the paper's geometry at NX x 0.8 NX (500, 1000, "
+                         "2000 or 4000), --study-m realizations (default 64) to t = 0.0035, then the "
+                         "centerline quantile diagnostics of Sec. 4 (p5..p95, width ratio, skewness "
+                         "of the bands, shear-layer onset, leading fringe)")
     ap.add_argument("--profile-launches", type=int, default=0,
                     help="profiling mode: initial datum, this many step launches and a "
                          "2 GiB device copy, no statistics and no JSON line")
@@ -184,6 +189,8 @@ def main() -> int:
         return run_c5(args, torch, vlbm, inputs)
     if args.w12:
         return run_w12(args, torch, vlbm)
+    if args.centerline:
+        return run_centerline(args, torch, vlbm, inputs)
 
     if args.profile_launches > 0:
         params = vlbm.Params.jet(precision=args.precision if args.precision != "both" else "fp64")
@@ -494,6 +501,108 @@ def run_study(args, torch, vlbm, inputs) -> int:
                             for p, v in (("cauchy", convergence.cauchy_pairs(len(shapes) - 1)),
                                          ("reference", convergence.reference_pairs(len(shapes) - 1)))},
                   "checkpoints": rows},
+    }
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+def run_centerline(args, torch, vlbm, inputs) -> int:
+    """Centerline diagnostics of Sec. 4 on the paper's geometry at t = 0.0035:
+    per node of the row next to the axis (y = +dx/2) the ensemble mean and
+    std, the empirical quantiles p5, p16, p50, p84, p95 (eq:empcdf) and the
+    width ratio Q (eq:widthratio), all from the library's kernels; then the
+    summary numbers the paper quotes: the onset of the shear-layer spread
+    (first x where the std exceeds three times the inlet's 0.30), the peak std
+    and the mean there, the leading fringe (last x where p95 exceeds twice the
+    ambient density) with the largest Q near it, and, over the mixing region
+    (std > 1 and p16 > twice the ambient density), the medians of Q and of
+    (p95 - mean) / (mean - p5)."""
+    import numpy as np
+
+    w = inputs.PAPER_GRIDS[f"paper{args.centerline}"]
+    M = args.study_m or 64
+    t_final = inputs.PAPER_CHECKPOINTS[-1]
+    precision = args.precision if args.precision != "both" else "fp64"
+    params = vlbm.Params.jet(precision=precision)
+    stream = torch.cuda.current_stream()
+    coefs = inputs.kl_coefficients(inputs.DEFAULT_SEED, 0, M)
+    level = [(w.nx, w.ny, w.dx, w.y_min)]
+    if not args.no_tune:
+        ens = vlbm.Ensemble(params, level, coefs, M)
+        ens.autotune(t_final, 4)
+        ens.close()
+        del ens
+    ens = vlbm.Ensemble(params, level, coefs, M)
+    t0 = time.perf_counter()
+    launches = 0
+    while launches == 0 or not done:
+        done = ens.step(t_final, args.chunk)
+        launches += args.chunk
+        progress(f"centerline: {launches} launches")
+    t, s, a, status = ens.times(0)
+    if np.any(status != 0) or np.any(t != t_final):
+        print(json.dumps({"error": "the ensemble did not reach t_final cleanly"}))
+        return 1
+    step_s = time.perf_counter() - t0
+    ncell = w.nx * w.ny
+    dev = dict(dtype=torch.float64, device="cuda")
+    acc = torch.empty((3, 2, ncell), **dev)
+    smp = torch.empty((M, ncell), **dev)
+    vlbm.vlbm_ensemble_stats(ens.h, 0, 1, acc, 0, smp, 0)
+    ens.close()
+    mean = torch.empty((3, ncell), **dev)
+    std = torch.empty_like(mean)
+    vlbm.vlbm_stats_finalize(acc, ncell, M, mean, std, stream)
+    j = w.ny // 2  # y = y_min + (j + 1/2) dx = +dx/2
+    row = smp[:, j * w.nx:(j + 1) * w.nx].contiguous()
+    del smp
+    vlbm.vlbm_sort_samples(row, w.nx, M, stream)
+    pct = [5, 16, 50, 84, 95]
+    qs = torch.empty((len(pct), w.nx), **dev)
+    vlbm.vlbm_quantiles(row, w.nx, M, pct, qs, stream)
+    q = torch.empty(w.nx, **dev)
+    vlbm.vlbm_width_ratio(row, w.nx, M, q, stream)
+    torch.cuda.synchronize()
+    mu = mean[0, j * w.nx:(j + 1) * w.nx].cpu().numpy()
+    sd = std[0, j * w.nx:(j + 1) * w.nx].cpu().numpy()
+    p5, p16, p50, p84, p95 = qs.cpu().numpy()
+    Q = q.cpu().numpy()
+    x = (np.arange(w.nx) + 0.5) * w.dx
+    rho_amb = params.rho_amb
+    onset = np.nonzero(sd > 3 * 0.30)[0]
+    fringe = np.nonzero(p95 > 2 * rho_amb)[0]
+    i_f = int(fringe.max()) if fringe.size else -1
+    near = slice(max(i_f - 40, 0), min(i_f + 41, w.nx)) if i_f >= 0 else slice(0, 0)
+    Qn = Q[near]
+    mix = (sd > 1.0) & (p16 > 2 * rho_amb)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        skew = (p95 - mu) / (mu - p5)
+    step = max(w.nx // 40, 1)
+    out = {
+        "metric": "centerline quantile diagnostics (Sec. 4)", "value": None, "unit": None, "n_gpus": 1,
+        "steps": 1, "warmup": 0, "ms_per_step": round(step_s * 1e3, 1), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64" if precision == "fp64" else "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": f"{w.name}: the paper's domain [0,2.5]x[-1,1] at {w.nx}x{w.ny}, M={M}, "
+                               f"t={t_final:g}, alpha={params.alpha:.4g}, row y=+dx/2", "launches": launches,
+                   "time_steps_per_realization": [int(s.min()), int(s.max())]},
+        "diagnostics": {
+            "shear_layer_onset_x": float(x[onset[0]]) if onset.size else None,
+            "peak_std": float(sd.max()), "mean_at_peak_std": float(mu[int(sd.argmax())]),
+            "x_peak_std": float(x[int(sd.argmax())]),
+            "leading_fringe_x": float(x[i_f]) if i_f >= 0 else None,
+            "max_Q_near_fringe": float(np.nanmax(Qn[np.isfinite(Qn)])) if np.any(np.isfinite(Qn)) else None,
+            "mixing_region_nodes": int(mix.sum()),
+            "median_Q_mixing_region": float(np.median(Q[mix])) if mix.any() else None,
+            "median_band_skew_mixing_region": float(np.median(skew[mix])) if mix.any() else None,
+            "laminar_core_std_x_0.2_to_0.8": float(sd[(x > 0.2) & (x < 0.8)].mean()),
+            "laminar_core_mean_x_0.2_to_0.8": float(mu[(x > 0.2) & (x < 0.8)].mean()),
+        },
+        "profile": {"x": [round(float(v), 4) for v in x[::step]],
+                    "mean": [round(float(v), 4) for v in mu[::step]], "std": [round(float(v), 4) for v in sd[::step]],
+                    **{f"p{k}": [round(float(v), 4) for v in arr[::step]]
+                       for k, arr in zip(pct, (p5, p16, p50, p84, p95))},
+                    "Q": [None if not np.isfinite(v) else round(float(v), 4) for v in Q[::step]]},
     }
     print(json.dumps(out), flush=True)
     return 0
