@@ -61,3 +61,56 @@ def test_laminar_core_carries_the_inlet_randomness(axis_profiles):
     std = a[:, i0:i1].std(axis=0)
     assert np.all(np.abs(mean / 5.0 - 1.0) < 0.06), mean.min()
     assert np.all(np.abs(std / SIGMA_AXIS - 1.0) < 0.25), (std.min(), std.max())
+
+
+def test_centerline_quantile_diagnostics_paper_geometry():
+    """Sec. 4 on the paper's domain at 1000x800 with 64 realizations to
+    t = 0.0035, through the library's statistics, sort, quantile and
+    width-ratio kernels, on the row next to the axis.  The paper (4000x3200,
+    M = 1000) reports a laminar core with std ~0.30 and mean ~5, the leading
+    fringe at x ~ 2.27 where the width ratio Q grows far beyond its Gaussian
+    1.654, a Gaussian Q (median ~1.67) inside the mixing region and positively
+    skewed bands there (median (p95 - mean)/(mean - p5) ~ 1.4; 1.2 at this
+    resolution, 1.45 at 2000x1600).  Bounds allow for the coarser grid and the
+    64 samples."""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    w = inputs.PAPER_GRIDS["paper1000"]
+    M, t_final = 64, 0.0035
+    coefs = inputs.kl_coefficients(inputs.DEFAULT_SEED, 0, M)
+    ens = vlbm.Ensemble(vlbm.Params.jet(), [(w.nx, w.ny, w.dx, w.y_min)], coefs, M)
+    ens.run(t_final, chunk=240)
+    t, s, a, status = ens.times(0)
+    assert np.all(status == 0) and np.all(t == t_final)
+    ncell = w.nx * w.ny
+    acc = torch.empty((3, 2, ncell), dtype=torch.float64, device="cuda")
+    smp = torch.empty((M, ncell), dtype=torch.float64, device="cuda")
+    vlbm.vlbm_ensemble_stats(ens.h, 0, 1, acc, 0, smp, 0)
+    ens.close()
+    mean = torch.empty((3, ncell), dtype=torch.float64, device="cuda")
+    std = torch.empty_like(mean)
+    vlbm.vlbm_stats_finalize(acc, ncell, M, mean, std)
+    j = w.ny // 2
+    row = smp[:, j * w.nx:(j + 1) * w.nx].contiguous()
+    vlbm.vlbm_sort_samples(row, w.nx, M)
+    qs = torch.empty((5, w.nx), dtype=torch.float64, device="cuda")
+    vlbm.vlbm_quantiles(row, w.nx, M, [5, 16, 50, 84, 95], qs)
+    q = torch.empty(w.nx, dtype=torch.float64, device="cuda")
+    vlbm.vlbm_width_ratio(row, w.nx, M, q)
+    torch.cuda.synchronize()
+    mu = mean[0, j * w.nx:(j + 1) * w.nx].cpu().numpy()
+    sd = std[0, j * w.nx:(j + 1) * w.nx].cpu().numpy()
+    p5, p16, p50, p84, p95 = qs.cpu().numpy()
+    Q = q.cpu().numpy()
+    x = (np.arange(w.nx) + 0.5) * w.dx
+    core = (x > 0.2) & (x < 0.8)
+    assert abs(sd[core].mean() / SIGMA_AXIS - 1.0) < 0.25
+    assert abs(mu[core].mean() / 5.0 - 1.0) < 0.1
+    i_f = int(np.nonzero(p95 > 1.0)[0].max())  # twice the ambient density
+    assert 2.15 < x[i_f] < 2.40, x[i_f]
+    near = Q[max(i_f - 20, 0):i_f + 21]
+    assert np.nanmax(near[np.isfinite(near)]) > 10.0
+    mix = (sd > 1.0) & (p16 > 1.0)
+    assert mix.sum() > 100
+    assert 1.45 < np.median(Q[mix]) < 1.90
+    assert np.median((p95[mix] - mu[mix]) / (mu[mix] - p5[mix])) > 1.0
