@@ -540,3 +540,38 @@ def test_checkpoint_resume_is_bitwise(precision):
         for x, y in zip(b.times(l)[:3], want[l][1][:3]):
             assert np.array_equal(x, y)
     b.close()
+
+
+def test_mixed_vs_fp64_statistics_jet640_early():
+    """The benchmark workload (640 x 320, 64 realizations) at t = 1e-4: the mixed
+    variant's one-point W1 against the FP64 ensemble (same seeds) is below
+    1e-3 of the mean density, and so is the mean-field difference; the std
+    fields, small over most of the domain, within 2e-2 (relative L1)."""
+    w = inputs.WORKLOADS["jet640"]
+    R, t_final = w.m, 1e-4
+    coefs = inputs.kl_coefficients(inputs.DEFAULT_SEED, 0, R)
+    ncell = (w.nx // 2) * (w.ny // 2)
+    res = {}
+    for prec in ("fp64", "mixed"):
+        ens = vlbm.Ensemble(vlbm.Params.jet(precision=prec), [(w.nx, w.ny, w.dx, w.y_min)], coefs, R)
+        ens.run(t_final, chunk=64)
+        acc = torch.empty((3, 2, ncell), dtype=torch.float64, device="cuda")
+        smp = torch.empty((R, ncell), dtype=torch.float64, device="cuda")
+        vlbm.vlbm_ensemble_stats(ens.h, 0, 2, acc, 0, smp, 0)
+        mean = torch.empty((3, ncell), dtype=torch.float64, device="cuda")
+        std = torch.empty_like(mean)
+        vlbm.vlbm_stats_finalize(acc, ncell, R, mean, std)
+        vlbm.vlbm_sort_samples(smp, ncell, R)
+        res[prec] = (mean, std, smp)
+        ens.close()
+    w1c = torch.empty(ncell, dtype=torch.float64, device="cuda")
+    w1m = torch.zeros(1, dtype=torch.float64, device="cuda")
+    vlbm.vlbm_w1(res["fp64"][2], res["mixed"][2], ncell, R, w1c, w1m)
+    torch.cuda.synchronize()
+    m64, s64 = res["fp64"][0].cpu().numpy(), res["fp64"][1].cpu().numpy()
+    mmx, smx = res["mixed"][0].cpu().numpy(), res["mixed"][1].cpu().numpy()
+    ew = w1m.item() / m64[0].mean()
+    em = max(_rel_l1(mmx[f], m64[f]) for f in range(3))
+    es = max(_rel_l1(smx[f], s64[f]) for f in range(3))
+    print(f"jet640 t=1e-4 mixed vs fp64: W1/mean(rho) {ew:.3e}, mean {em:.3e}, std {es:.3e}")
+    assert ew < 1e-3 and em < 1e-3 and es < 2e-2
