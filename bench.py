@@ -348,6 +348,18 @@ def main() -> int:
                      "frac_of_device_copy": round(r0["achieved"] / copy_gbs, 4)},
         "w1_rerun": r0["w1_rerun"],
     }
+
+    def add_hbm(roof, precision):
+        """Measured HBM bytes per node update (counters, per launch of all R x nx x
+        ny updates) and the HBM rate they imply at the measured kernel speed."""
+        tr = roof.get("traffic")
+        if tr:
+            per_lup = tr / (R * w.nx * w.ny)
+            roof["hbm_bytes_per_node_update"] = round(per_lup, 1)
+            roof["hbm_GBs_implied"] = round(roof["achieved"] * per_lup / BYTES_PER_LUP[precision], 1)
+
+    add_hbm(out["roofline"], head)
+
     def stat_errors(a, b):
         """mean/std rel. L1 per field and W1 / mean density between two runs' final
         ensembles (a is the reference)."""
@@ -413,6 +425,7 @@ def main() -> int:
             "step_kernel_rows_per_wave": rm["tuned_rows"],
             "phases_ms_per_step": rm["phases_ms"],
         }
+        add_hbm(out["mixed"]["roofline"], "mixed")
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w)
     print(json.dumps(out), flush=True)
