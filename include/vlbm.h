@@ -127,6 +127,20 @@ typedef struct vlbm_ensemble vlbm_ensemble;
 /* Message for the calling thread's last failed call (never NULL). */
 const char *vlbm_last_error(void);
 
+/*
+ * The random draw omega_m of the initial measure (eq:karhunenExp, Sec. 2.3):
+ * the KL coefficients of realizations first .. first + count - 1 into the
+ * HOST array out [count][2 * modes] (row layout Y_1, Z_1, Y_2, Z_2, ..., each
+ * in [-1, 1)), the input vlbm_init_ensemble takes.  Coefficient c of
+ * realization m is 2 u - 1 with u the top 53 bits of output number
+ * m * 2 * modes + c (0-based) of a SplitMix64 generator seeded with `seed`
+ * (Steele, Lea & Flood 2014), so a realization's sample depends on (seed, m)
+ * only: batches and prefixes of an ensemble see the same samples (the nested
+ * sample sets of Sec. 3.1).  0 <= modes <= 64.  Host arithmetic only.
+ */
+vlbm_status vlbm_kl_coefficients(uint64_t seed, int64_t first, int32_t count, int32_t modes,
+                                 double *out);
+
 /* Bytes of ONE state buffer for R realizations of an nx x ny level. */
 vlbm_status vlbm_state_bytes(const vlbm_params *p, int32_t nx, int32_t ny, int32_t n_real,
                              size_t *bytes);
@@ -210,16 +224,19 @@ vlbm_status vlbm_moments(const vlbm_ensemble *e, int32_t level, double *rho, dou
  * Every realization's density, speed and pressure are restricted to the
  * coarse grid by r x r block averaging (Sec. 3.2; r >= 1 divides nx and ny;
  * n_cells = (ny/r)(nx/r)), then merged into the running accumulator acc:
- *   acc: DEVICE double [3 field][2][n_cells]: per field (rho, |v|, p) the
+ *   acc: DEVICE double [3 field][2][acc_cells]: per field (rho, |v|, p) the
  *        running mean and the sum of squared deviations M2 of the
  *        n_prev realizations merged so far (contents ignored when n_prev = 0).
+ *        acc_cells must equal n_cells (else VLBM_ERR_SIZE).
  *        Batches are merged with the pairwise update of Chan, Golub & LeVeque.
- *   samples: DEVICE double [m_total][n_cells] or NULL; receives the restricted
- *        density of realization m in row m_offset + m (input of the one-point
- *        Wasserstein distance).  The caller guarantees m_offset + n_real <= m_total.
+ *   samples: DEVICE double [sample_rows][n_cells] or NULL; receives the
+ *        restricted density of realization m in row m_offset + m (input of the
+ *        one-point Wasserstein distance).  m_offset + n_real > sample_rows is
+ *        rejected with VLBM_ERR_SIZE before anything is enqueued.
  */
 vlbm_status vlbm_ensemble_stats(const vlbm_ensemble *e, int32_t level, int32_t r, double *acc,
-                                int64_t n_prev, double *samples, int64_t m_offset);
+                                int64_t acc_cells, int64_t n_prev, double *samples,
+                                int64_t sample_rows, int64_t m_offset);
 
 /*
  * Mean and population standard deviation (eq:mean, eq:std: sqrt(M2 / n))
@@ -240,8 +257,10 @@ vlbm_status vlbm_sort_samples(double *samples, int64_t n_cells, int32_t m, void 
  * One-point Wasserstein-1 distance (eq:w1disc) between two sorted sample
  * stores of equal size [m][n_cells]: w1_cell[k] = (1/m) sum_m |a_(m) - b_(m)|
  * (DEVICE [n_cells] or NULL) and its average over cells, W_{1,1} (DEVICE
- * scalar or NULL; needs w1_cell, which it averages in a fixed order).
- * Enqueued on hip_stream.
+ * scalar or NULL), summed in a fixed order that depends on n_cells only.  The
+ * average needs a workspace of n_cells / 1024 partial sums, taken as
+ * stream-ordered device memory on hip_stream (hipMallocAsync) and released on
+ * it.  Enqueued on hip_stream.
  */
 vlbm_status vlbm_w1(const double *sorted_a, const double *sorted_b, int64_t n_cells, int32_t m,
                     double *w1_cell, double *w1_mean, void *hip_stream);
@@ -269,6 +288,8 @@ vlbm_status vlbm_strong_error(const double *a, const double *b, int64_t n_cells,
  * out[0] = (1/n) sum_i |x_i - y_i| over the n cells of the common grid: the
  * error of eq:mean when x, y are the two ensemble-mean density fields, of
  * eq:std for the two standard-deviation fields.  y = NULL gives (1/n) sum |x_i|.
+ * Two-stage fixed-order sum; its workspace of n / 1024 partial sums is taken
+ * as stream-ordered device memory on hip_stream and released on it.
  */
 vlbm_status vlbm_mean_abs_diff(const double *x, const double *y, int64_t n, double *out,
                                void *hip_stream);

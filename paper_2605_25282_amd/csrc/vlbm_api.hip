@@ -33,9 +33,11 @@ template <int PREC>
 __global__ void stats_accumulate_kernel(PhysArgs, LevelArgs, Ctl, int, int, double *, long long, double *, long long);
 __global__ void stats_finalize_kernel(const double *, long long, long long, double *, double *);
 template <int CPB> __global__ void sort_samples_kernel(double *, long long, int, int);
-__global__ void w1_kernel(const double *, const double *, long long, int, double *, double *);
-__global__ void scale_kernel(double *, double);
-void launch_mean_abs_diff(const double *x, const double *y, long long n, double *out, hipStream_t st);
+long long reduction_partials(long long n);
+void launch_mean_abs_diff(const double *x, const double *y, long long n, double *out, double *partials,
+                          hipStream_t st);
+void launch_w1(const double *a, const double *b, long long ncell, int m, double *w1_cell, double *w1_mean,
+               double *partials, hipStream_t st);
 void launch_strong_error(const double *a, const double *b, long long ncell, int m, double *per_real,
                          double *out, hipStream_t st);
 void launch_quantiles(const double *sorted, long long ncell, int m, const int *pct, int n_q, double *out,
@@ -43,7 +45,6 @@ void launch_quantiles(const double *sorted, long long ncell, int m, const int *p
 void launch_width_ratio(const double *sorted, long long ncell, int m, double *q, hipStream_t st);
 void launch_w12(const double *a, const double *b, int ncx, int ncy, int m, int n_pd, double *w_pair,
                 double *w_mean, hipStream_t st);
-__global__ void fill_kernel(double *, double);
 } // namespace vlbm
 
 using namespace vlbm;
@@ -303,6 +304,29 @@ vlbm_status read_ctl(const vlbm_ensemble *e, std::vector<double> &t, std::vector
 extern "C" {
 
 const char *vlbm_last_error(void) { return g_err.c_str(); }
+
+vlbm_status vlbm_kl_coefficients(uint64_t seed, int64_t first, int32_t count, int32_t modes, double *out)
+{
+    if (!out)
+        return fail(VLBM_ERR_ARG, "out is NULL");
+    if (first < 0 || count < 0 || modes < 0 || modes > 64)
+        return fail(VLBM_ERR_ARG, "need first >= 0, count >= 0 and 0 <= modes <= 64");
+    // SplitMix64 (Steele, Lea & Flood 2014) in counter mode: draw n of the stream
+    // seeded with `seed` is the mixing function applied to seed + (n + 1) G.
+    const uint64_t G = 0x9E3779B97F4A7C15ull;
+    const uint64_t per = 2ull * (uint64_t)modes;
+    for (int64_t k = 0; k < count; ++k)
+        for (uint64_t c = 0; c < per; ++c) {
+            const uint64_t n = ((uint64_t)first + (uint64_t)k) * per + c;
+            uint64_t z = seed + (n + 1ull) * G;
+            z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+            z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+            z = z ^ (z >> 31);
+            const double u = (double)(z >> 11) * (1.0 / 9007199254740992.0); // top 53 bits, [0, 1)
+            out[k * (int64_t)per + (int64_t)c] = 2.0 * u - 1.0;
+        }
+    return VLBM_OK;
+}
 
 vlbm_status vlbm_state_bytes(const vlbm_params *p, int32_t nx, int32_t ny, int32_t n_real, size_t *bytes)
 {
@@ -691,8 +715,8 @@ vlbm_status vlbm_moments(const vlbm_ensemble *e, int32_t level, double *rho, dou
     return VLBM_OK;
 }
 
-vlbm_status vlbm_ensemble_stats(const vlbm_ensemble *e, int32_t level, int32_t r, double *acc,
-                                int64_t n_prev, double *samples, int64_t m_offset)
+vlbm_status vlbm_ensemble_stats(const vlbm_ensemble *e, int32_t level, int32_t r, double *acc, int64_t acc_cells,
+                                int64_t n_prev, double *samples, int64_t sample_rows, int64_t m_offset)
 {
     vlbm_status rc = check_level(e, level);
     if (rc != VLBM_OK)
@@ -700,11 +724,17 @@ vlbm_status vlbm_ensemble_stats(const vlbm_ensemble *e, int32_t level, int32_t r
     const LevelArgs &L = e->levels[level];
     if (r < 1 || L.nx % r || L.ny % r)
         return fail(VLBM_ERR_ARG, "restriction factor %d must divide %d x %d", r, L.nx, L.ny);
+    const long long ncell = (long long)(L.nx / r) * (L.ny / r);
     if (!acc)
         return fail(VLBM_ERR_ARG, "acc is NULL");
+    if (acc_cells != ncell)
+        return fail(VLBM_ERR_SIZE, "acc holds %lld cells per field, the %d x %d level restricted by %d has %lld",
+                    (long long)acc_cells, L.nx, L.ny, r, ncell);
     if (n_prev < 0 || m_offset < 0)
         return fail(VLBM_ERR_ARG, "n_prev and m_offset must be >= 0");
-    const long long ncell = (long long)(L.nx / r) * (L.ny / r);
+    if (samples && m_offset + L.R > sample_rows)
+        return fail(VLBM_ERR_SIZE, "sample store of %lld rows cannot take rows %lld .. %lld",
+                    (long long)sample_rows, (long long)m_offset, (long long)(m_offset + L.R - 1));
     const PhysArgs ph = phys_args(e->p);
     const dim3 grid((unsigned)((ncell + 255) / 256));
     if (e->p.precision == VLBM_FP64)
@@ -753,19 +783,43 @@ vlbm_status vlbm_sort_samples(double *samples, int64_t n_cells, int32_t m, void 
     return VLBM_OK;
 }
 
-vlbm_status vlbm_w1(const double *a, const double *b, int64_t n_cells, int32_t m, double *w1_cell,
-                    double *w1_mean, void *hip_stream)
+namespace {
+// Stage-1 partial sums of a two-stage reduction: stream-ordered device memory,
+// released on the same stream once the reduction has consumed it.
+struct StreamScratch {
+    double *p = nullptr;
+    hipStream_t st = nullptr;
+    ~StreamScratch()
+    {
+        if (p)
+            (void)hipFreeAsync(p, st);
+    }
+};
+
+vlbm_status check_w1_args(const double *a, const double *b, int64_t n_cells, int32_t m)
 {
     if (!a || !b)
         return fail(VLBM_ERR_ARG, "sample stores must be non-NULL");
     if (n_cells < 1 || m < 1)
-        return fail(VLBM_ERR_SIZE, "need n_cells >= 1 and m >= 1");
-    if (w1_mean && !w1_cell)
-        return fail(VLBM_ERR_ARG, "w1_mean needs w1_cell (the per-cell values are averaged in a fixed order)");
+        return fail(VLBM_ERR_SIZE, "need n_cells >= 1 and m >= 1 (got %lld, %d)", (long long)n_cells, m);
+    return VLBM_OK;
+}
+} // namespace
+
+vlbm_status vlbm_w1(const double *a, const double *b, int64_t n_cells, int32_t m, double *w1_cell,
+                    double *w1_mean, void *hip_stream)
+{
+    vlbm_status rc = check_w1_args(a, b, n_cells, m);
+    if (rc != VLBM_OK)
+        return rc;
+    if (!w1_cell && !w1_mean)
+        return VLBM_OK;
     hipStream_t st = (hipStream_t)hip_stream;
-    w1_kernel<<<(unsigned)((n_cells + 255) / 256), 256, 0, st>>>(a, b, n_cells, m, w1_cell, nullptr);
+    StreamScratch ws;
+    ws.st = st;
     if (w1_mean)
-        launch_mean_abs_diff(w1_cell, nullptr, n_cells, w1_mean, st);
+        HIP_TRY(hipMallocAsync((void **)&ws.p, (size_t)reduction_partials(n_cells) * sizeof(double), st));
+    launch_w1(a, b, n_cells, m, w1_cell, w1_mean, ws.p, st);
     LAUNCH_CHECK("w1");
     return VLBM_OK;
 }
@@ -788,7 +842,11 @@ vlbm_status vlbm_mean_abs_diff(const double *x, const double *y, int64_t n, doub
         return fail(VLBM_ERR_ARG, "x and out must be non-NULL");
     if (n < 1)
         return fail(VLBM_ERR_SIZE, "need n >= 1");
-    launch_mean_abs_diff(x, y, n, out, (hipStream_t)hip_stream);
+    hipStream_t st = (hipStream_t)hip_stream;
+    StreamScratch ws;
+    ws.st = st;
+    HIP_TRY(hipMallocAsync((void **)&ws.p, (size_t)reduction_partials(n) * sizeof(double), st));
+    launch_mean_abs_diff(x, y, n, out, ws.p, st);
     LAUNCH_CHECK("mean_abs_diff");
     return VLBM_OK;
 }

@@ -564,44 +564,6 @@ __global__ void __launch_bounds__(256) sort_samples_kernel(double *samples, long
     }
 }
 
-__global__ void __launch_bounds__(256) w1_kernel(const double *__restrict__ a,
-                                                 const double *__restrict__ b, long long ncell,
-                                                 int m, double *w1_cell, double *w1_sum)
-{
-    const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    double w = 0.0;
-    if (c < ncell) {
-        for (int k = 0; k < m; ++k)
-            w += fabs(a[(size_t)k * ncell + c] - b[(size_t)k * ncell + c]);
-        w = w / (double)m;
-        if (w1_cell)
-            w1_cell[c] = w;
-    }
-    if (w1_sum) {
-        __shared__ double red[4];
-#pragma unroll
-        for (int o = 32; o > 0; o >>= 1)
-            w += __shfl_xor(w, o, 64);
-        if ((threadIdx.x & 63) == 0)
-            red[threadIdx.x >> 6] = w;
-        __syncthreads();
-        if (threadIdx.x == 0)
-            atomicAdd(w1_sum, (red[0] + red[1]) + (red[2] + red[3]));
-    }
-}
-
-__global__ void scale_kernel(double *x, double s)
-{
-    if (threadIdx.x == 0 && blockIdx.x == 0)
-        x[0] = x[0] * s;
-}
-
-__global__ void fill_kernel(double *x, double v)
-{
-    if (threadIdx.x == 0 && blockIdx.x == 0)
-        x[0] = v;
-}
-
 // Explicit instantiations.
 template __global__ void init_macro_kernel<0>(PhysArgs, LevelArgs, const double *, Ctl);
 template __global__ void init_macro_kernel<1>(PhysArgs, LevelArgs, const double *, Ctl);

@@ -29,16 +29,77 @@ __device__ __forceinline__ double block_sum(double v, double *lds)
     return lds[0];
 }
 
-// out[0] = (1/n) sum_i |x_i - y_i|  (y == nullptr: (1/n) sum_i |x_i|).
-// One block: statistics fields are small next to the ensemble state.
-__global__ void __launch_bounds__(RED_THREADS) mean_abs_diff_kernel(const double *__restrict__ x,
-                                                                    const double *__restrict__ y,
-                                                                    long long n, double *out)
+// ---------------------------------------------------------------------------
+// Two-stage reductions over fields of common-grid cells (up to the 12.8 M nodes
+// of the largest level).  Stage 1: block b reduces the contiguous range
+// [b * RED_CHUNK, (b + 1) * RED_CHUNK) -- each thread a strided sum, then a fixed
+// tree in LDS -- into partials[b].  Stage 2: one block sums the partials the
+// same way and divides by the element count.  The order depends on n only, so
+// equal inputs give equal bits, and the work is spread over n / RED_CHUNK
+// blocks instead of one compute unit.
+// ---------------------------------------------------------------------------
+static constexpr int RED_CHUNK = 1024;      // elements per stage-1 block
+static constexpr int PART_THREADS = 256;    // threads per stage-1 block
+
+long long reduction_partials(long long n) { return (n + RED_CHUNK - 1) / RED_CHUNK; }
+
+// partials[b] = sum over the block's range of |x_i - y_i| (|x_i| if y is null)
+__global__ void __launch_bounds__(PART_THREADS) abs_partial_kernel(const double *__restrict__ x,
+                                                                   const double *__restrict__ y,
+                                                                   long long n, double *__restrict__ partials)
+{
+    __shared__ double lds[PART_THREADS];
+    const long long i0 = (long long)blockIdx.x * RED_CHUNK;
+    double s = 0.0;
+    for (int k = threadIdx.x; k < RED_CHUNK; k += PART_THREADS) {
+        const long long i = i0 + k;
+        if (i < n)
+            s += fabs(y ? x[i] - y[i] : x[i]);
+    }
+    const double tot = block_sum<PART_THREADS>(s, lds);
+    if (threadIdx.x == 0)
+        partials[blockIdx.x] = tot;
+}
+
+// One-point W1 of eq:w1disc per cell from two sorted stores [m][ncell]:
+// w1_cell[c] = (1/m) sum_k |a_(k) - b_(k)| (if w1_cell is not null), and the
+// block's sum of these values into partials[b] (if partials is not null).
+__global__ void __launch_bounds__(PART_THREADS) w1_partial_kernel(const double *__restrict__ a,
+                                                                  const double *__restrict__ b,
+                                                                  long long ncell, int m,
+                                                                  double *__restrict__ w1_cell,
+                                                                  double *__restrict__ partials)
+{
+    __shared__ double lds[PART_THREADS];
+    const long long c0 = (long long)blockIdx.x * RED_CHUNK;
+    double s = 0.0;
+    for (int k = threadIdx.x; k < RED_CHUNK; k += PART_THREADS) {
+        const long long c = c0 + k;
+        if (c < ncell) {
+            double w = 0.0;
+            for (int q = 0; q < m; ++q)
+                w += fabs(a[(size_t)q * ncell + c] - b[(size_t)q * ncell + c]);
+            w = w / (double)m;
+            if (w1_cell)
+                w1_cell[c] = w;
+            s += w;
+        }
+    }
+    if (!partials)
+        return;
+    const double tot = block_sum<PART_THREADS>(s, lds);
+    if (threadIdx.x == 0)
+        partials[blockIdx.x] = tot;
+}
+
+// out[0] = (sum of the np values in partials) / n, in a fixed order.
+__global__ void __launch_bounds__(RED_THREADS) finish_mean_kernel(const double *__restrict__ partials,
+                                                                  long long np, long long n, double *out)
 {
     __shared__ double lds[RED_THREADS];
     double s = 0.0;
-    for (long long i = threadIdx.x; i < n; i += RED_THREADS)
-        s += fabs(y ? x[i] - y[i] : x[i]);
+    for (long long i = threadIdx.x; i < np; i += RED_THREADS)
+        s += partials[i];
     const double tot = block_sum<RED_THREADS>(s, lds);
     if (threadIdx.x == 0)
         out[0] = tot / (double)n;
@@ -291,16 +352,30 @@ __host__ __device__ inline int quantile_row(int pct, int m) { return (int)(((lon
 // ---------------------------------------------------------------------------
 // Launchers (called by the C ABI in vlbm_api.hip after argument validation).
 // ---------------------------------------------------------------------------
-void launch_mean_abs_diff(const double *x, const double *y, long long n, double *out, hipStream_t st)
+// Workspace of the stage-1 partial sums: `partials` holds at least
+// reduction_partials(n) doubles (caller-provided or the static workspace).
+void launch_mean_abs_diff(const double *x, const double *y, long long n, double *out, double *partials,
+                          hipStream_t st)
 {
-    mean_abs_diff_kernel<<<1, RED_THREADS, 0, st>>>(x, y, n, out);
+    const long long np = reduction_partials(n);
+    abs_partial_kernel<<<(unsigned)np, PART_THREADS, 0, st>>>(x, y, n, partials);
+    finish_mean_kernel<<<1, RED_THREADS, 0, st>>>(partials, np, n, out);
+}
+
+void launch_w1(const double *a, const double *b, long long ncell, int m, double *w1_cell, double *w1_mean,
+               double *partials, hipStream_t st)
+{
+    const long long np = reduction_partials(ncell);
+    w1_partial_kernel<<<(unsigned)np, PART_THREADS, 0, st>>>(a, b, ncell, m, w1_cell, w1_mean ? partials : nullptr);
+    if (w1_mean)
+        finish_mean_kernel<<<1, RED_THREADS, 0, st>>>(partials, np, ncell, w1_mean);
 }
 
 void launch_strong_error(const double *a, const double *b, long long ncell, int m, double *per_real,
                          double *out, hipStream_t st)
 {
     strong_error_kernel<<<m, 256, 0, st>>>(a, b, ncell, per_real);
-    mean_abs_diff_kernel<<<1, RED_THREADS, 0, st>>>(per_real, nullptr, m, out);
+    finish_mean_kernel<<<1, RED_THREADS, 0, st>>>(per_real, m, m, out);
 }
 
 void launch_quantiles(const double *sorted, long long ncell, int m, const int *pct, int n_q, double *out,
@@ -327,7 +402,7 @@ void launch_w12(const double *a, const double *b, int ncx, int ncy, int m, int n
     else
         w12_kernel<256, 4><<<P, 256, lds, st>>>(a, b, ncx, ncy, m, n_pd, w_pair);
     if (w_mean)
-        mean_abs_diff_kernel<<<1, RED_THREADS, 0, st>>>(w_pair, nullptr, (long long)P, w_mean);
+        finish_mean_kernel<<<1, RED_THREADS, 0, st>>>(w_pair, (long long)P, (long long)P, w_mean);
 }
 
 void launch_width_ratio(const double *sorted, long long ncell, int m, double *q, hipStream_t st)

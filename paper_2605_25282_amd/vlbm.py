@@ -92,7 +92,8 @@ def lib():
             "vlbm_times": ([_VP, i32, _DP, ctypes.POINTER(i64), _DP, ctypes.POINTER(i32)], i32),
             "vlbm_get_state": ([_VP, i32, _VP], i32),
             "vlbm_moments": ([_VP, i32, _VP, _VP, _VP], i32),
-            "vlbm_ensemble_stats": ([_VP, i32, i32, _VP, i64, _VP, i64], i32),
+            "vlbm_ensemble_stats": ([_VP, i32, i32, _VP, i64, i64, _VP, i64, i64], i32),
+            "vlbm_kl_coefficients": ([ctypes.c_uint64, i64, i32, i32, _DP], i32),
             "vlbm_stats_finalize": ([_VP, i64, i64, _VP, _VP, _VP], i32),
             "vlbm_sort_samples": ([_VP, i64, i32, _VP], i32),
             "vlbm_w1": ([_VP, _VP, i64, i32, _VP, _VP, _VP], i32),
@@ -126,6 +127,23 @@ def _check(rc: int) -> None:
 def _ptr(t) -> _VP:
     """Device pointer of a torch tensor (or None)."""
     return None if t is None else _VP(t.data_ptr())
+
+
+def _f64(t, numel: int, name: str) -> _VP:
+    """Device pointer of a contiguous float64 CUDA tensor holding at least numel
+    values (None passes through); anything else raises before the call."""
+    if t is None:
+        return None
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name}: expected a CUDA tensor")
+    if t.dtype != torch.float64:
+        raise TypeError(f"{name}: expected float64, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name}: tensor must be contiguous")
+    if t.numel() < numel:
+        raise ValueError(f"{name}: needs {numel} values, tensor holds {t.numel()}")
+    return _VP(t.data_ptr())
 
 
 def _stream(stream=None) -> _VP:
@@ -194,45 +212,63 @@ def vlbm_moments(h, level: int, rho=None, speed=None, p=None) -> None:
 
 def vlbm_ensemble_stats(h, level: int, r: int, acc, n_prev: int, samples=None,
                         m_offset: int = 0) -> None:
-    _check(lib().vlbm_ensemble_stats(h, level, r, _ptr(acc), n_prev, _ptr(samples), m_offset))
+    """acc: float64 [3][2][n_cells]; samples: float64 [rows][n_cells] (rows >=
+    m_offset + n_real), n_cells = (nx/r)(ny/r) of the level."""
+    if acc is None or acc.dim() < 1 or acc.numel() % 6:
+        raise ValueError("acc must be a float64 tensor of 6 * n_cells values")
+    cells = acc.numel() // 6
+    rows = 0
+    if samples is not None:
+        if samples.numel() % cells:
+            raise ValueError("samples must hold whole rows of n_cells values")
+        rows = samples.numel() // cells
+    _check(lib().vlbm_ensemble_stats(h, level, r, _f64(acc, 6 * cells, "acc"), cells, n_prev,
+                                     _f64(samples, rows * cells, "samples"), rows, m_offset))
 
 
-def vlbm_stats_finalize(acc, n_cells: int, n_total: int, mean=None, std=None, stream=None) -> None:
-    _check(lib().vlbm_stats_finalize(_ptr(acc), n_cells, n_total, _ptr(mean), _ptr(std),
-                                     _stream(stream)))
+def vlbm_kl_coefficients(seed: int, first: int, count: int, modes: int = 10) -> np.ndarray:
+    """KL coefficients of realizations first .. first+count-1, shape (count, 2 modes)."""
+    out = np.zeros((count, 2 * modes))
+    _check(lib().vlbm_kl_coefficients(seed & 0xFFFFFFFFFFFFFFFF, first, count, modes,
+                                      out.ctypes.data_as(_DP)))
+    return out
 
 
 def vlbm_sort_samples(samples, n_cells: int, m: int, stream=None) -> None:
-    _check(lib().vlbm_sort_samples(_ptr(samples), n_cells, m, _stream(stream)))
+    _check(lib().vlbm_sort_samples(_f64(samples, n_cells * m, "samples"), n_cells, m, _stream(stream)))
 
 
 def vlbm_w1(a, b, n_cells: int, m: int, w1_cell=None, w1_mean=None, stream=None) -> None:
-    _check(lib().vlbm_w1(_ptr(a), _ptr(b), n_cells, m, _ptr(w1_cell), _ptr(w1_mean),
+    _check(lib().vlbm_w1(_f64(a, n_cells * m, "a"), _f64(b, n_cells * m, "b"), n_cells, m,
+                         _f64(w1_cell, n_cells, "w1_cell"), _f64(w1_mean, 1, "w1_mean"),
                          _stream(stream)))
 
 
 def vlbm_strong_error(a, b, n_cells: int, m: int, per_real, out, stream=None) -> None:
-    _check(lib().vlbm_strong_error(_ptr(a), _ptr(b), n_cells, m, _ptr(per_real), _ptr(out),
-                                   _stream(stream)))
+    _check(lib().vlbm_strong_error(_f64(a, n_cells * m, "a"), _f64(b, n_cells * m, "b"), n_cells, m,
+                                   _f64(per_real, m, "per_real"), _f64(out, 1, "out"), _stream(stream)))
 
 
 def vlbm_mean_abs_diff(x, y, n: int, out, stream=None) -> None:
-    _check(lib().vlbm_mean_abs_diff(_ptr(x), _ptr(y), n, _ptr(out), _stream(stream)))
+    _check(lib().vlbm_mean_abs_diff(_f64(x, n, "x"), _f64(y, n, "y"), n, _f64(out, 1, "out"),
+                                    _stream(stream)))
 
 
 def vlbm_quantiles(sorted_samples, n_cells: int, m: int, pct, out, stream=None) -> None:
     pc = (ctypes.c_int32 * len(pct))(*[int(x) for x in pct])
-    _check(lib().vlbm_quantiles(_ptr(sorted_samples), n_cells, m, pc, len(pct), _ptr(out),
-                                _stream(stream)))
+    _check(lib().vlbm_quantiles(_f64(sorted_samples, n_cells * m, "sorted"), n_cells, m, pc, len(pct),
+                                _f64(out, len(pct) * n_cells, "out"), _stream(stream)))
 
 
 def vlbm_width_ratio(sorted_samples, n_cells: int, m: int, q, stream=None) -> None:
-    _check(lib().vlbm_width_ratio(_ptr(sorted_samples), n_cells, m, _ptr(q), _stream(stream)))
+    _check(lib().vlbm_width_ratio(_f64(sorted_samples, n_cells * m, "sorted"), n_cells, m,
+                                  _f64(q, n_cells, "q"), _stream(stream)))
 
 
 def vlbm_w12(a, b, ncx: int, ncy: int, m: int, n_pd: int, w_pair, w_mean=None, stream=None) -> None:
-    _check(lib().vlbm_w12(_ptr(a), _ptr(b), ncx, ncy, m, n_pd, _ptr(w_pair), _ptr(w_mean),
-                          _stream(stream)))
+    cells = ncx * ncy
+    _check(lib().vlbm_w12(_f64(a, cells * m, "a"), _f64(b, cells * m, "b"), ncx, ncy, m, n_pd,
+                          _f64(w_pair, n_pd ** 4, "w_pair"), _f64(w_mean, 1, "w_mean"), _stream(stream)))
 
 
 def vlbm_rate_fit(errors, dx) -> tuple[float, float]:

@@ -99,7 +99,7 @@ def test_null_handles_rejected(lib):
     assert lib.vlbm_step(None, 1.0, 1, None) == vlbm.ERR_ARG
     assert lib.vlbm_set_state(None, 0, None, None, None, None) == vlbm.ERR_ARG
     assert lib.vlbm_moments(None, 0, None, None, None) == vlbm.ERR_ARG
-    assert lib.vlbm_ensemble_stats(None, 0, 1, None, 0, None, 0) == vlbm.ERR_ARG
+    assert lib.vlbm_ensemble_stats(None, 0, 1, None, 0, 0, None, 0, 0) == vlbm.ERR_ARG
     assert lib.vlbm_sort_samples(None, 1, 1, None) == vlbm.ERR_ARG
     assert lib.vlbm_w1(None, None, 1, 1, None, None, None) == vlbm.ERR_ARG
     assert lib.vlbm_stats_finalize(None, 1, 1, None, None, None) == vlbm.ERR_ARG
@@ -158,10 +158,59 @@ def test_observable_entry_points_validate_before_launch(lib):
     assert lib.vlbm_quantiles(fake, 10, 4, pct, 9, fake, None) == vlbm.ERR_ARG
     assert lib.vlbm_quantiles(fake, 0, 4, pct, 1, fake, None) == vlbm.ERR_SIZE
     assert lib.vlbm_width_ratio(fake, 10, 0, fake, None) == vlbm.ERR_SIZE
-    assert lib.vlbm_w1(fake, fake, 10, 4, None, fake, None) == vlbm.ERR_ARG  # mean needs per-cell
+    assert lib.vlbm_w1(fake, fake, 0, 4, None, fake, None) == vlbm.ERR_SIZE
+    assert lib.vlbm_w1(fake, fake, 10, 0, fake, fake, None) == vlbm.ERR_SIZE
     assert lib.vlbm_w12(None, fake, 10, 10, 4, 3, fake, None, None) == vlbm.ERR_ARG
     assert lib.vlbm_w12(fake, fake, 10, 10, 4, 3, None, None, None) == vlbm.ERR_ARG
     assert lib.vlbm_w12(fake, fake, 10, 10, 1025, 3, fake, None, None) == vlbm.ERR_SIZE
     assert lib.vlbm_w12(fake, fake, 10, 10, 0, 3, fake, None, None) == vlbm.ERR_SIZE
     assert lib.vlbm_w12(fake, fake, 10, 2, 4, 3, fake, None, None) == vlbm.ERR_ARG  # n_pd > ncy
     assert lib.vlbm_w12(fake, fake, 10, 10, 4, 0, fake, None, None) == vlbm.ERR_ARG
+
+
+# SplitMix64 test vector: the first five outputs of the generator seeded with
+# 1234567, as published with the reference implementation of Steele, Lea and
+# Flood's generator (the splitmix64.c that accompanies xoshiro).
+_SPLITMIX64_1234567 = [6457827717110365317, 3203168211198807973, 9817491932198370423,
+                       4593380528125082431, 16408922859458223821]
+
+
+def test_kl_coefficients_follow_the_published_generator(lib):
+    """vlbm_kl_coefficients draws coefficient c of realization m from output
+    m * 2K + c of SplitMix64: its first values for seed 1234567 are the published
+    outputs mapped to [-1, 1) by their top 53 bits."""
+    got = vlbm.vlbm_kl_coefficients(1234567, 0, 1, modes=3)[0]
+    want = [2.0 * ((z >> 11) / 2.0 ** 53) - 1.0 for z in _SPLITMIX64_1234567]
+    assert list(got[:5]) == want
+    # output n of realization m sits at column n - m * 2K
+    got2 = vlbm.vlbm_kl_coefficients(1234567, 1, 1, modes=2)[0]
+    assert got2[0] == want[4]
+
+
+def test_kl_coefficients_nested_and_equal_to_the_input_generator(lib):
+    """(seed, m) fixes realization m's draw whatever the batch (Sec. 3.1's nested
+    sample sets), and the library's draws are those of the seeded input module."""
+    from paper_2605_25282_amd import inputs
+    full = vlbm.vlbm_kl_coefficients(inputs.DEFAULT_SEED, 0, 40)
+    part = vlbm.vlbm_kl_coefficients(inputs.DEFAULT_SEED, 17, 9)
+    assert np.array_equal(full[17:26], part)
+    assert np.array_equal(full, inputs.kl_coefficients(inputs.DEFAULT_SEED, 0, 40))
+    assert np.all(full >= -1.0) and np.all(full < 1.0)
+    assert lib.vlbm_kl_coefficients(1, 0, 1, 65, ctypes.cast(ctypes.c_void_p(4096), ctypes.POINTER(ctypes.c_double))) == vlbm.ERR_ARG
+    assert lib.vlbm_kl_coefficients(1, -1, 1, 2, None) == vlbm.ERR_ARG
+
+
+def test_binding_refuses_tensors_that_do_not_fit():
+    """The binding checks dtype, device, contiguity and size before it hands a
+    pointer to the library (a float32 or short buffer would otherwise be written
+    out of bounds by the device)."""
+    torch = pytest.importorskip("torch")
+    with pytest.raises(TypeError):
+        vlbm._f64(torch.zeros(10, dtype=torch.float64), 10, "x")  # host tensor
+    if torch.cuda.is_available():
+        with pytest.raises(TypeError):
+            vlbm._f64(torch.zeros(10, dtype=torch.float32, device="cuda"), 10, "x")
+        with pytest.raises(ValueError):
+            vlbm._f64(torch.zeros(9, dtype=torch.float64, device="cuda"), 10, "x")
+        with pytest.raises(ValueError):
+            vlbm._f64(torch.zeros((4, 4), dtype=torch.float64, device="cuda").t(), 16, "x")
