@@ -1,0 +1,254 @@
+"""Long-horizon GPU parity against the CPU oracle, through the C ABI: whole
+runs to the benchmark's final time t = 1e-3 (hundreds to thousands of steps,
+past the formation of the bow shock and the onset of the shear-layer
+instability), and the paper's own domain and grids (Sec. 2.2, Sec. 3.3).
+
+Bars: the state per (variable, slot) plane to 1e-11 relative (the FP64 and
+mixed paths are built to be bitwise equal to the oracle, so the observed
+difference is reported too), identical step counts, final times and last
+kinetic speeds; the ensemble statistics of Sec. 3.4 (eq:mean, eq:std,
+eq:w1disc) element by element to 1e-3 relative.  The oracle runs on the host's
+cores while the GPU works; nothing it consumes comes from the GPU."""
+import os
+import time
+from concurrent.futures import ThreadPoolExecutor, wait
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import oracle as O
+from paper_2605_25282_amd import inputs, vlbm
+
+TOL = 1e-11
+STAT_TOL = 1e-3
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    vlbm.lib()
+    yield
+    torch.cuda.synchronize()
+
+
+def _threads():
+    return max(1, min(16, os.cpu_count() or 1))
+
+
+def _start_oracle(jobs):
+    """Start oracle runs (p, grid, coef, t_final) on host threads; returns futures of
+    (state, t, steps, a_last, status)."""
+    ex = ThreadPoolExecutor(max_workers=_threads())
+
+    def one(job):
+        p, g, coef, t_final = job
+        return O.run(p, g, O.init(p, g, coef), t_final)
+
+    futs = [ex.submit(one, j) for j in jobs]
+    ex.shutdown(wait=False)
+    return futs
+
+
+def _results(futs, label):
+    """Wait for oracle runs, printing progress every 30 s (long runs stay visibly alive)."""
+    t0 = time.time()
+    pending = set(futs)
+    while pending:
+        _, pending = wait(pending, timeout=30)
+        print(f"[{label}] {len(futs) - len(pending)}/{len(futs)} oracle runs done after "
+              f"{time.time() - t0:.0f} s", flush=True)
+    return [f.result() for f in futs]
+
+
+def _to_oracle(gpu_state, m):
+    s = gpu_state[:, :, m]
+    return s.transpose(1, 0, 2, 3).reshape(20, s.shape[2], s.shape[3])
+
+
+def _plane_err(mine, ref):
+    worst = 0.0
+    for s in range(5):
+        for v in range(4):
+            d = np.abs(mine[s * 4 + v] - ref[s * 4 + v]).max()
+            den = np.abs(ref[s * 4 + v]).max()
+            if den == 0.0:
+                den = np.abs(ref[s * 4 + 3]).max()
+            worst = max(worst, d / den)
+    return worst
+
+
+def _check_level(ens, level, refs, t_final):
+    """State parity and identical clocks of every realization of one level."""
+    st = ens.state(level).cpu().numpy()
+    t, s, a, status = ens.times(level)
+    assert np.all(status == 0)
+    worst, maxdiff = 0.0, 0.0
+    for m, r in enumerate(refs):
+        r_st, r_t, r_n, r_a, rc = r
+        assert rc == O.OK
+        assert s[m] == r_n and t[m] == r_t == t_final and a[m] == r_a, m
+        mine = _to_oracle(st, m)
+        worst = max(worst, _plane_err(mine, r_st))
+        maxdiff = max(maxdiff, float(np.abs(mine - r_st).max()))
+    print(f"level {ens.shapes[level]}: steps {s.min()}..{s.max()}, worst plane rel err "
+          f"{worst:.3e}, max abs diff {maxdiff:.3e}")
+    assert worst <= TOL
+    return st, s
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_jet128_to_t_1e3(precision):
+    """The 128 x 64 jet, all 8 realizations, to t = 1e-3 (about 400 steps: the bow
+    shock crosses the domain and leaves through the outflow layer)."""
+    w = inputs.WORKLOADS["jet128"]
+    g = O.Grid(w.nx, w.ny, w.dx, w.y_min)
+    R, t_final = 8, 1e-3
+    coefs = inputs.kl_coefficients(inputs.DEFAULT_SEED, 0, R)
+    p = O.Params(storage=precision)
+    futs = _start_oracle([(p, g, coefs[m], t_final) for m in range(R)])
+    ens = vlbm.Ensemble(vlbm.Params.jet(precision=precision), [(w.nx, w.ny, w.dx, w.y_min)], coefs, R)
+    ens.run(t_final, chunk=120)
+    _, steps = _check_level(ens, 0, _results(futs, 'jet128'), t_final)
+    ens.close()
+    assert steps.min() > 300
+
+
+def _gpu_stats(ens, level, r, M):
+    """Restricted mean/std of (rho, |v|, p) and the sorted restricted density samples."""
+    nx, ny = ens.shapes[level]
+    nc = (nx // r) * (ny // r)
+    dev = dict(dtype=torch.float64, device="cuda")
+    acc = torch.empty((3, 2, nc), **dev)
+    smp = torch.empty((M, nc), **dev)
+    vlbm.vlbm_ensemble_stats(ens.h, level, r, acc, 0, smp, 0)
+    mean, std = torch.empty((3, nc), **dev), torch.empty((3, nc), **dev)
+    vlbm.vlbm_stats_finalize(acc, nc, M, mean, std)
+    vlbm.vlbm_sort_samples(smp, nc, M)
+    return mean, std, smp
+
+
+def _oracle_stats(p, states, r):
+    fields = [O.restrict(f, r) for f in O.moments(p, states[:, 0:4])]
+    mean = np.stack([O.ensemble_mean(f).ravel() for f in fields])
+    std = np.stack([O.ensemble_std(f).ravel() for f in fields])
+    return mean, std, fields[0].reshape(states.shape[0], -1)
+
+
+def _elementwise(got, ref, scale):
+    """max over cells of |got - ref| / (|ref| + 1e-12 scale): element by element."""
+    return float((np.abs(got - ref) / (np.abs(ref) + 1e-12 * scale)).max())
+
+
+def test_jet640_and_jet320_to_t_1e3_with_statistics():
+    """The benchmark workload's grid: 640 x 320 and its 320 x 160 partner on the
+    same 8 seeds, one launch per step of both levels, to t = 1e-3 (about 2100 and
+    1050 steps).  Every realization's state against the oracle's; then mean and
+    std of (rho, |v|, p) at r = 1 and r = 2 (Sec. 3.2 restriction), the per-cell
+    one-point W1 (eq:w1disc) between the GPU and oracle ensembles (0 when the
+    states agree), and the W1 between the two levels on the 320 x 160 grid,
+    each element by element against the oracle's."""
+    R, t_final = 8, 1e-3
+    fine = inputs.WORKLOADS["jet640"]
+    coarse = inputs.WORKLOADS["jet320"]
+    works = [coarse, fine]
+    coefs = inputs.kl_coefficients(inputs.DEFAULT_SEED, 0, R)
+    p = O.Params()
+    grids = [O.Grid(w.nx, w.ny, w.dx, w.y_min) for w in works]
+    futs = [_start_oracle([(p, g, coefs[m], t_final) for m in range(R)]) for g in grids]
+    ens = vlbm.Ensemble(vlbm.Params.jet(), [(w.nx, w.ny, w.dx, w.y_min) for w in works], coefs, R)
+    ens.run(t_final, chunk=240)
+    refs = [_results(fs, f'jet640 level {l}') for l, fs in enumerate(futs)]
+    for l in range(2):
+        _, steps = _check_level(ens, l, refs[l], t_final)
+        assert steps.min() > (1900 if l == 1 else 950)
+    ref_states = [np.stack([r[0] for r in refs[l]]) for l in range(2)]
+    sorted_at = {}
+    for l, r in ((1, 1), (1, 2), (0, 1)):
+        mean, std, smp = _gpu_stats(ens, l, r, R)
+        r_mean, r_std, r_rho = _oracle_stats(p, ref_states[l], r)
+        scale = np.abs(r_mean).max(axis=1, keepdims=True)
+        for f in range(3):
+            e_mean = _elementwise(mean[f].cpu().numpy(), r_mean[f], scale[f])
+            e_std = _elementwise(std[f].cpu().numpy(), r_std[f], scale[f])
+            print(f"level {l} r={r} field {f}: mean {e_mean:.2e}, std {e_std:.2e}")
+            assert e_mean <= STAT_TOL and e_std <= STAT_TOL, (l, r, f)
+        r_sorted = np.sort(r_rho, axis=0)
+        nc = r_sorted.shape[1]
+        w1c = torch.empty(nc, dtype=torch.float64, device="cuda")
+        vlbm.vlbm_w1(smp, torch.tensor(r_sorted, device="cuda"), nc, R, w1c, None)
+        torch.cuda.synchronize()
+        w1_vs_oracle = w1c.cpu().numpy()
+        assert w1_vs_oracle.max() <= STAT_TOL * np.abs(r_mean[0]).mean()
+        sorted_at[(l, r)] = (smp, r_rho)
+    # one-point W1 between the levels on the 320 x 160 grid (eq:w1disc)
+    (a_gpu, a_ref), (b_gpu, b_ref) = sorted_at[(0, 1)], sorted_at[(1, 2)]
+    nc = a_ref.shape[1]
+    w1c = torch.empty(nc, dtype=torch.float64, device="cuda")
+    w1m = torch.zeros(1, dtype=torch.float64, device="cuda")
+    vlbm.vlbm_w1(a_gpu, b_gpu, nc, R, w1c, w1m)
+    torch.cuda.synchronize()
+    ref_w1 = O.w1(a_ref, b_ref)
+    e_w1 = _elementwise(w1c.cpu().numpy(), ref_w1, np.abs(ref_w1).max())
+    print(f"W1 between levels: mean {w1m.item():.6g} (oracle {ref_w1.mean():.6g}), elementwise {e_w1:.2e}")
+    assert e_w1 <= STAT_TOL
+    assert w1m.item() == pytest.approx(O.w11(a_ref, b_ref), rel=STAT_TOL)
+    ens.close()
+
+
+def _paper(nx):
+    w = inputs.PAPER_GRIDS[f"paper{nx}"]
+    return w, O.Grid(w.nx, w.ny, w.dx, w.y_min)
+
+
+def test_paper_domain_500x400_to_first_checkpoint():
+    """The paper's domain [0, 2.5] x [-1, 1] (Sec. 2.2) at its coarsest study grid
+    500 x 400, 4 realizations, to its first checkpoint t = 0.0005 (Tab. 1)."""
+    R, t_final = 4, inputs.PAPER_CHECKPOINTS[0]
+    w, g = _paper(500)
+    coefs = inputs.kl_coefficients(inputs.DEFAULT_SEED, 0, R)
+    futs = _start_oracle([(O.Params(), g, coefs[m], t_final) for m in range(R)])
+    ens = vlbm.Ensemble(vlbm.Params.jet(), [(w.nx, w.ny, w.dx, w.y_min)], coefs, R)
+    ens.run(t_final, chunk=120)
+    _check_level(ens, 0, _results(futs, 'paper500'), t_final)
+    ens.close()
+
+
+def test_paper_domain_observables_500_vs_1000():
+    """The five observables of the convergence study (eq:w1disc, eq:w2, eq:mean,
+    eq:std, eq:strongError) between 500 x 400 and 1000 x 800 on the paper's
+    domain, 4 realizations with the same seeds, at t = 1e-4, from the library's
+    kernels against the oracle's from its own runs."""
+    from paper_2605_25282_amd import convergence
+
+    R, t_final = 4, 1e-4
+    (wc, gc), (wf, gf) = _paper(500), _paper(1000)
+    coefs = inputs.kl_coefficients(inputs.DEFAULT_SEED, 0, R)
+    p = O.Params()
+    futs = [_start_oracle([(p, g, coefs[m], t_final) for m in range(R)]) for g in (gc, gf)]
+    levels = [(w.nx, w.ny, w.dx, w.y_min) for w in (wc, wf)]
+    ens = vlbm.Ensemble(vlbm.Params.jet(), levels, coefs, R)
+    ens.run(t_final, chunk=120)
+    st = convergence.study(ens, [wc.dx, wf.dx], n_pd=10)
+    refs = [_results(fs, f'paper level {l}') for l, fs in enumerate(futs)]
+    for l in range(2):
+        _check_level(ens, l, refs[l], t_final)
+    ens.close()
+    rho = []
+    for l, r in ((0, 1), (1, 2)):
+        states = np.stack([x[0] for x in refs[l]])
+        rho.append(O.restrict(O.moments(p, states[:, 0:4])[0], r))
+    ref = {
+        "W11": O.w11(rho[0], rho[1]),
+        "W12": O.w12(rho[0], rho[1], n_pd=10)[0],
+        "E_mean": O.cell_mean_abs_diff(O.ensemble_mean(rho[0]), O.ensemble_mean(rho[1])),
+        "E_std": O.cell_mean_abs_diff(O.ensemble_std(rho[0]), O.ensemble_std(rho[1])),
+        "E_strong": O.strong_error(rho[0], rho[1]),
+    }
+    for name, val in ref.items():
+        got = st.errors[("cauchy", name)][0]
+        print(f"{name}: gpu {got:.10g} oracle {val:.10g}")
+        assert val > 0 and got == pytest.approx(val, rel=1e-10), name
