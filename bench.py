@@ -1,26 +1,32 @@
 """Benchmark of the VLBM Mach-2000 jet ensemble hot path on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--precision fp64|mixed]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--precision both|fp64|mixed]
 
-By default both storage precisions run: the FP64 pipeline gives the headline
-value and the mixed one (populations' rho, rho v in FP32) is reported beside it,
-with its speedup and the mean/std/W1 errors of its final ensemble against the
-FP64 ensemble of the same run.
+The default workload is the largest configuration that fits one GPU: the
+5056 x 2528 level with its 2528 x 1264 partner on the same seeds (the pair
+whose one-point W1 the refinement study needs), M = 1000 realizations streamed
+through HBM in batches.  One benchmark step is one slice of that job on one
+batch of B realizations (B the largest batch HBM holds next to the job's
+sample stores): a fixed block of step launches (fused collide-stream kernel
+with the kinetic-speed reduction and the boundary layers, both levels in each
+launch, hipGraph replays), then the batch's statistics -- moments and
+conservative restriction of both levels to the 2528 x 1264 grid, Chan merge
+into the running mean/std accumulators, scatter of the restricted densities
+into the M = 1000 sample stores at the batch's rows, the per-cell sort of
+those rows and the one-point W1 between the levels.
 
-One benchmark step is one pass of the whole hot path over one ensemble of
-synthetic realizations of the jet workload (640 x 320 nodes, M = 64, to
-t = 1e-3): initial datum, time stepping (fused collide-stream kernel with the
-kinetic-speed reduction and boundary layers), moments, conservative
-restriction, ensemble mean and standard deviation of (rho, |v|, p), the
-restricted density samples, their per-cell sort, and the one-point W1 against
-the previous step's sorted store (identical seeds: W1 must be exactly 0, a
-run-to-run determinism check).
+Both storage precisions run by default: FP64 gives the headline value, the
+mixed variant (populations' rho, rho v in FP32) is reported beside it, and the
+statistics of a mixed ensemble are compared with an FP64 ensemble of the same
+seeds (640 x 320, M = 64, t = 1e-5, 1e-4, 1e-3) next to the round-off floor:
+an FP64 ensemble whose inlet densities are moved by one ulp.
 
 Prints one JSON line.  `value` is ensemble GLUPS: node updates summed over
-realizations per second of the whole step.  `roofline` reports the step
-kernel: algorithmic 320 B per FP64 node update (224 B mixed) over its average
-launch duration, measured with HIP events on the stream the kernels run on.
-`cpu_baseline` times the CPU oracle on a bounded sample on this host.
+realizations and levels per second of the timed steps.  `roofline` reports the
+step kernel: algorithmic 320 B per FP64 node update (224 B mixed) over its
+average launch duration, measured with HIP events on the stream the kernels
+run on.  `cpu_baseline` times the CPU oracle on a bounded sample of the same
+grid on this host.
 """
 from __future__ import annotations
 
@@ -68,28 +74,38 @@ def measured_traffic(precision: str, workload: str):
     return d.get("bytes_per_launch")
 
 
-def cpu_baseline(workload, seconds_target: float = 15.0):
-    """The oracle, as it stands, on a bounded sample of the same workload: the first
-    realizations of the ensemble on the full grid for a fixed number of steps."""
-    import numpy as np
-
+def cpu_baseline(name, nx, ny, dx, y_min, steps=None, seconds_target: float = 15.0,
+                 mem_budget: float = 120e9):
+    """The oracle, as it stands, on a bounded sample of the same grid: the first
+    realizations of the ensemble for a fixed number of steps, one realization per
+    host thread (the oracle parallelizes over realizations only).  Threads: the
+    host share of one GPU (OMP_NUM_THREADS, at most 16), fewer if one
+    realization's oracle working set (state, step copy and per-node Maxwellians,
+    about 820 B per node) times the threads would exceed mem_budget bytes."""
     import oracle as O
     from paper_2605_25282_amd import inputs
 
-    # the host share of one GPU: OMP_NUM_THREADS where the machine sets it
-    threads = min(int(os.environ.get("OMP_NUM_THREADS", "8") or 8), os.cpu_count() or 1, 16)
+    share = min(int(os.environ.get("OMP_NUM_THREADS", "8") or 8), os.cpu_count() or 1, 16)
+    per_real = 820.0 * nx * ny
+    threads = max(1, min(share, int(mem_budget // per_real)))
     p = O.Params()
-    g = O.Grid(workload.nx, workload.ny, workload.dx, workload.y_min)
+    g = O.Grid(nx, ny, dx, y_min)
     coefs = inputs.kl_coefficients(inputs.DEFAULT_SEED, 0, threads)
-    # size the sample from a short probe so that it takes ~seconds_target
+    if steps is None:
+        # size the sample from a short probe so that it takes ~seconds_target
+        t0 = time.perf_counter()
+        O.run(p, g, O.init(p, g, coefs[0]), 1e30, max_steps=2)
+        per_step = (time.perf_counter() - t0) / 2
+        steps = int(max(4, min(200, seconds_target / max(per_step, 1e-6))))
+    from concurrent.futures import ThreadPoolExecutor
+    with ThreadPoolExecutor(max_workers=threads) as ex:
+        st0 = list(ex.map(lambda m: O.init(p, g, coefs[m]), range(threads)))
     t0 = time.perf_counter()
-    O.run(p, g, O.init(p, g, coefs[0]), 1e30, max_steps=2)
-    per_step = (time.perf_counter() - t0) / 2
-    steps = int(max(4, min(200, seconds_target / max(per_step, 1e-6))))
-    t0 = time.perf_counter()
-    states, t, n, status = O.run_ensemble(p, g, coefs, 1e30, max_steps=steps, threads=threads)
+    with ThreadPoolExecutor(max_workers=threads) as ex:
+        n = list(ex.map(lambda m: O.run(p, g, st0[m], 1e30, max_steps=steps)[2], range(threads)))
     el = time.perf_counter() - t0
-    lups = float(n.sum()) * workload.nx * workload.ny
+    del st0
+    lups = float(sum(n)) * nx * ny
     model = "unknown"
     try:
         with open("/proc/cpuinfo") as f:
@@ -101,8 +117,9 @@ def cpu_baseline(workload, seconds_target: float = 15.0):
         pass
     return {"value": lups / el / 1e9, "unit": "GLUPS", "cores": threads, "kind": "oracle",
             "cpu_model": model, "host_cpus": os.cpu_count(),
-            "sample": f"{threads} realizations x {steps} steps of the {workload.nx}x{workload.ny} "
-                      f"jet on {threads} host threads ({el:.1f} s, {lups:.3e} node updates)"}
+            "sample": f"{threads} realizations x {steps} steps of the {nx}x{ny} {name} grid on "
+                      f"{threads} host threads, the stepping timed ({el:.1f} s, "
+                      f"{lups:.3e} node updates)"}
 
 
 def progress(msg: str) -> None:
@@ -116,16 +133,27 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--precision", default="both", choices=["both", "fp64", "mixed"])
-    ap.add_argument("--workload", default="jet640")
-    ap.add_argument("--chunk", type=int, default=240, help="launches per vlbm_step call")
+    ap.add_argument("--workload", default="c5",
+                    help="c5 (default): the 5056x2528 level and its 2528x1264 partner, M = 1000 "
+                         "streamed in batches; or the name of a single-level jet workload "
+                         "(jet128, jet320, jet640, jet1280), one step = one whole pass to t_final")
+    ap.add_argument("--launches", type=int, default=60,
+                    help="c5: step launches per benchmark step")
+    ap.add_argument("--batch", type=int, default=0,
+                    help="c5: realizations per batch (0: the largest that fits in HBM, at most 64)")
+    ap.add_argument("--chunk", type=int, default=240, help="launches per vlbm_step call (whole passes)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-mixed-error", action="store_true",
+                    help="c5: skip the mixed-vs-FP64 statistics comparison")
     ap.add_argument("--no-tune", action="store_true",
                     help="skip the autotuning pass (with --chunk-rows: a fixed step-kernel "
                          "configuration, e.g. for a profiler run of this same command)")
     ap.add_argument("--chunk-rows", type=int, default=0,
                     help="rows per wave of the step kernel (0: autotuned / default)")
-    ap.add_argument("--copy-probe", action="store_true",
-                    help="also run one device copy of known size (counter calibration)")
+    ap.add_argument("--mixed-error", action="store_true",
+                    help="instead of the default line: statistics of a mixed and of a one-ulp-"
+                         "perturbed FP64 ensemble against an FP64 ensemble of the same seeds, at "
+                         "several times (--workload jet640 or jet1280)")
     ap.add_argument("--study", action="store_true",
                     help="instead of the default line: the three-level ensemble (320x160, "
                          "640x320, 1280x640, M=128, t=1e-3) advanced by one launch per step, "
@@ -136,9 +164,9 @@ def main() -> int:
     ap.add_argument("--study-m", type=int, default=0, help="realizations (0: 128 config, 32 paper)")
     ap.add_argument("--study-levels", type=int, default=3, choices=[3, 4],
                     help="paper geometry: 4 adds the 4000x3200 level (the paper's full hierarchy)")
-    ap.add_argument("--c5", action="store_true",
+    ap.add_argument("--c5-full", action="store_true",
                     help="instead of the default line: the largest level (5056x2528) with its "
-                         "2528x1264 partner on the same seeds, streamed in batches to t=1e-3 with "
+                         "2528x1264 partner on the same seeds, whole batches streamed to t=1e-3 with "
                          "running mean/std and sample stores, then the one-point W1 between the levels")
     ap.add_argument("--c5-batches", type=int, default=2)
     ap.add_argument("--c5-batch-m", type=int, default=16)
@@ -152,15 +180,14 @@ def main() -> int:
                          "centerline quantile diagnostics of Sec. 4 (p5..p95, width ratio, skewness "
                          "of the bands, shear-layer onset, leading fringe)")
     ap.add_argument("--profile-launches", type=int, default=0,
-                    help="profiling mode: initial datum, this many step launches and a "
-                         "2 GiB device copy, no statistics and no JSON line")
+                    help="profiling mode: initial datum and this many step launches of the "
+                         "workload (c5: one batch, both levels), no statistics and no JSON line")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; multi-GPU runs are not "
                                    "supported (--gpus must be 1)"}))
         return 2
 
-    import numpy as np
     import torch
 
     from paper_2605_25282_amd import inputs, vlbm
@@ -169,6 +196,321 @@ def main() -> int:
         print(json.dumps({"error": "no GPU visible"}))
         return 2
     vlbm.lib()  # fails loudly if the HIP library was not built
+    if args.study:
+        return run_study(args, torch, vlbm, inputs)
+    if args.c5_full:
+        return run_c5(args, torch, vlbm, inputs)
+    if args.w12:
+        return run_w12(args, torch, vlbm)
+    if args.centerline:
+        return run_centerline(args, torch, vlbm, inputs)
+    if args.mixed_error:
+        w = inputs.WORKLOADS["jet640" if args.workload == "c5" else args.workload]
+        out = mixed_error_study(torch, vlbm, inputs, w, (0.01, 0.1, 1.0), args.chunk)
+        print(json.dumps({"mixed_error_study": out}), flush=True)
+        return 0
+    if args.workload == "c5":
+        return run_headline(args, torch, vlbm, inputs)
+    return run_pass(args, torch, vlbm, inputs)
+
+
+def copy_bandwidth(torch, nbytes: int = 1 << 31, reps: int = 5) -> float:
+    """Device-to-device copy rate (bytes read + written per second) of torch's
+    copy kernel, the practical HBM ceiling the step kernel is compared with."""
+    stream = torch.cuda.current_stream()
+    src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record(stream)
+    e1.synchronize()
+    gbs = 2 * nbytes * reps / (e0.elapsed_time(e1) / 1e3) / 1e9
+    del src, dst
+    torch.cuda.empty_cache()
+    return gbs
+
+
+def stat_errors(torch, vlbm, a, b, ncell_w1, R):
+    """mean/std rel. L1 per field and W1 / mean density between two ensembles'
+    statistics (a is the reference); sorted restricted density samples for W1."""
+    rel = lambda x, y: float((x - y).abs().sum() / y.abs().sum())
+    w1c = torch.empty(ncell_w1, dtype=torch.float64, device="cuda")
+    w1m = torch.zeros(1, dtype=torch.float64, device="cuda")
+    vlbm.vlbm_w1(a["sorted"], b["sorted"], ncell_w1, R, w1c, w1m)
+    torch.cuda.synchronize()
+    sig = lambda x: float(f"{x:.4g}")
+    return {"mean_rel_l1": [sig(rel(b["mean"][f], a["mean"][f])) for f in range(3)],
+            "std_rel_l1": [sig(rel(b["std"][f], a["std"][f])) for f in range(3)],
+            "w1_over_mean_rho": sig(float(w1m.item()) / float(a["mean"][0].mean())),
+            "fields": ["rho", "|v|", "p"]}
+
+
+def mixed_error_study(torch, vlbm, inputs, w, fracs, chunk):
+    """Ensemble statistics of the mixed variant against an FP64 ensemble of the
+    same seeds at t = frac * t_final, next to two references for the size of such
+    differences: the round-off floor (an FP64 ensemble of the same seeds whose
+    inlet densities are moved up by one ulp, which the Dirichlet inlet keeps
+    feeding in) and the sampling floor (an FP64 ensemble on the next M seeds).
+    Statistics: mean and std of (rho, |v|, p) on the nodes, W1 of the 2 x 2
+    restricted density."""
+    R, r_w1 = w.m, 2
+    ncell, ncell_w1 = w.nx * w.ny, (w.nx // r_w1) * (w.ny // r_w1)
+    dev = dict(dtype=torch.float64, device="cuda")
+
+    def run(precision, t_end, first_seed=0, ulp=False):
+        coefs = inputs.kl_coefficients(inputs.DEFAULT_SEED, first_seed, R)
+        ens = vlbm.Ensemble(vlbm.Params.jet(precision=precision), [(w.nx, w.ny, w.dx, w.y_min)], coefs, R)
+        if ulp:
+            st = ens.state(0)  # [4 var][5 slot][R][ny][nx]
+            col = st[0, 0, :, :, 0]
+            st[0, 0, :, :, 0] = torch.nextafter(col, torch.full_like(col, float("inf")))
+            t, s, a, _ = ens.times(0)
+            ens.set_state(0, st, t, s, a)
+            del st
+        ens.run(t_end, chunk=chunk)
+        t, s, a, status = ens.times(0)
+        if (status != 0).any() or (t != t_end).any():
+            raise RuntimeError(f"{precision} ensemble did not reach t = {t_end:g} cleanly")
+        acc = torch.empty((3, 2, ncell), **dev)
+        mean, std = torch.empty((3, ncell), **dev), torch.empty((3, ncell), **dev)
+        sacc = torch.empty((3, 2, ncell_w1), **dev)
+        smp = torch.empty((R, ncell_w1), **dev)
+        vlbm.vlbm_ensemble_stats(ens.h, 0, 1, acc, 0, None, 0)
+        vlbm.vlbm_stats_finalize(acc, ncell, R, mean, std)
+        vlbm.vlbm_ensemble_stats(ens.h, 0, r_w1, sacc, 0, smp, 0)
+        vlbm.vlbm_sort_samples(smp, ncell_w1, R)
+        ens.close()
+        return {"mean": mean, "std": std, "sorted": smp, "steps": [int(s.min()), int(s.max())]}
+
+    out = []
+    for frac in fracs:
+        t_e = w.t_final * frac
+        ref = run("fp64", t_e)
+        row = {"t": t_e, "time_steps_per_realization": ref["steps"],
+               "mixed_vs_fp64": stat_errors(torch, vlbm, ref, run("mixed", t_e), ncell_w1, R),
+               "fp64_one_ulp_inlet_vs_fp64": stat_errors(torch, vlbm, ref, run("fp64", t_e, ulp=True),
+                                                         ncell_w1, R),
+               "fp64_independent_seeds_vs_fp64": stat_errors(torch, vlbm, ref, run("fp64", t_e, first_seed=R),
+                                                             ncell_w1, R)}
+        out.append(row)
+        progress(f"mixed-error study: t={t_e:g} done")
+        torch.cuda.empty_cache()
+    return {"workload": f"{w.name}: {w.nx}x{w.ny}, M={R}, same seeds", "rows": out}
+
+
+C5_M_TOTAL = 1000          # realizations of the whole job
+C5_HEADROOM = 6 << 30      # device bytes left free next to the batch
+
+
+def c5_works(inputs):
+    fine = inputs.WORKLOADS["jet5056"]
+    coarse = inputs.JetWorkload("jet2528", fine.nx // 2, fine.ny // 2, fine.m, fine.t_final)
+    return [coarse, fine]
+
+
+def run_headline(args, torch, vlbm, inputs) -> int:
+    """The largest single-GPU configuration, one benchmark step = one slice of the
+    M = 1000 job on one batch: `launches` step launches of both levels, then the
+    batch's restriction, Chan merge, sample scatter, per-cell sort and the W1
+    between the levels."""
+    import numpy as np
+
+    works = c5_works(inputs)
+    coarse, fine = works
+    t_final = fine.t_final
+    levels = [(w.nx, w.ny, w.dx, w.y_min) for w in works]
+    ncx, ncy = coarse.nx, coarse.ny
+    ncell = ncx * ncy
+    stream = torch.cuda.current_stream()
+    dev = dict(dtype=torch.float64, device="cuda")
+    variants = ["fp64", "mixed"] if args.precision == "both" else [args.precision]
+    per_real = max(sum(2 * vlbm.vlbm_state_bytes(vlbm.Params.jet(precision=v), w.nx, w.ny, 1) for w in works)
+                   for v in variants)
+    lup_per_launch_per_real = sum(w.nx * w.ny for w in works)
+
+    if args.profile_launches > 0:
+        B = args.batch or 16
+        prec = variants[0]
+        ens = vlbm.Ensemble(vlbm.Params.jet(precision=prec), levels,
+                            vlbm.vlbm_kl_coefficients(inputs.DEFAULT_SEED, 0, B), B)
+        if args.chunk_rows:
+            ens.tune("march", args.chunk_rows)
+        ens.step(t_final, args.profile_launches, want_done=True)
+        ens.close()
+        torch.cuda.synchronize()
+        print(f"profiled {args.profile_launches} step launches of the 5056x2528 + 2528x1264 pair, "
+              f"{B} realizations, {prec}", flush=True)
+        return 0
+
+    # the job's statistics: running accumulators and the sample stores of all M realizations
+    stores = [torch.zeros((C5_M_TOTAL, ncell), **dev) for _ in works]
+    acc = [torch.empty((3, 2, ncell), **dev) for _ in works]
+    mean = [torch.empty((3, ncell), **dev) for _ in works]
+    std = [torch.empty((3, ncell), **dev) for _ in works]
+    w1c = torch.empty(ncell, **dev)
+    w1m = torch.zeros(1, **dev)
+    B = args.batch
+    if B <= 0:
+        free, _ = torch.cuda.mem_get_info()
+        B = int(max(1, min(64, (free - C5_HEADROOM) // per_real)))
+    slots = C5_M_TOTAL // B
+    L = args.launches
+    progress(f"c5: batch of {B} realizations ({per_real / 1e9:.2f} GB each), {L} launches per step")
+
+    def variant(prec):
+        params = vlbm.Params.jet(precision=prec)
+        coefs = vlbm.vlbm_kl_coefficients(inputs.DEFAULT_SEED, 0, B)
+        ens = vlbm.Ensemble(params, levels, coefs, B)
+        tuned = None
+        if not args.no_tune:
+            tuned = ens.autotune(t_final, 4)  # live steps, counted toward t_final
+            progress(f"{prec}: autotuned rows per wave {tuned}")
+        elif args.chunk_rows:
+            ens.tune("march", args.chunk_rows)
+        acc_step = {"step_ms": 0.0, "stats_s": 0.0}
+
+        def one_step(k, timed):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            ens.step(t_final, L, want_done=False)
+            e1.record(stream)
+            e1.synchronize()
+            c0 = time.perf_counter()
+            slot = k % slots
+            subs = []
+            for l, w in enumerate(works):
+                vlbm.vlbm_ensemble_stats(ens.h, l, w.nx // ncx, acc[l], slot * B, stores[l], slot * B)
+                sub = stores[l][slot * B:(slot + 1) * B]
+                vlbm.vlbm_sort_samples(sub, ncell, B, stream)
+                vlbm.vlbm_stats_finalize(acc[l], ncell, (slot + 1) * B, mean[l], std[l], stream)
+                subs.append(sub)
+            vlbm.vlbm_w1(subs[0], subs[1], ncell, B, w1c, w1m, stream)
+            torch.cuda.synchronize()
+            if timed:
+                acc_step["step_ms"] += e0.elapsed_time(e1)
+                acc_step["stats_s"] += time.perf_counter() - c0
+
+        for k in range(args.warmup):
+            one_step(k, False)
+            progress(f"{prec}: warmup step {k + 1}/{args.warmup} done")
+        s0 = [ens.times(l)[1].copy() for l in range(len(works))]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(args.steps):
+            one_step(args.warmup + k, True)
+            progress(f"{prec}: timed step {k + 1}/{args.steps} done")
+        torch.cuda.synchronize()
+        elapsed = time.perf_counter() - t0
+        lups, steps_range = 0.0, []
+        for l, w in enumerate(works):
+            t, s, a, status = ens.times(l)
+            if np.any(status != 0):
+                raise RuntimeError(f"{prec}: level {l} latched a failure")
+            lups += float((s - s0[l]).sum()) * w.nx * w.ny
+            steps_range.append([int(s.min()), int(s.max())])
+        t_reached = float(ens.times(1)[0].min())
+        ens.close()
+        del ens
+        torch.cuda.empty_cache()
+        n_launch = args.steps * L
+        achieved = BYTES_PER_LUP[prec] * lups / (acc_step["step_ms"] / 1e3) / 1e9 if acc_step["step_ms"] else 0.0
+        return {"value": lups / elapsed / 1e9 if elapsed > 0 else 0.0,
+                "ms_per_step": elapsed / max(args.steps, 1) * 1e3,
+                "achieved": achieved,
+                "avg_launch_ms": acc_step["step_ms"] / max(n_launch, 1),
+                "phases_ms": {"step_launches": round(acc_step["step_ms"] / max(args.steps, 1), 3),
+                              "statistics": round(acc_step["stats_s"] * 1e3 / max(args.steps, 1), 3)},
+                "tuned": tuned, "steps": steps_range, "t_reached": t_reached,
+                "w1_between_levels": float(w1m.item())}
+
+    res = {}
+    for v in variants:
+        res[v] = variant(v)
+    # once per job (untimed): sort of the whole M = 1000 store of each level and the W1
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for l in range(len(works)):
+        vlbm.vlbm_sort_samples(stores[l], ncell, C5_M_TOTAL, stream)
+    vlbm.vlbm_w1(stores[0], stores[1], ncell, C5_M_TOTAL, w1c, w1m, stream)
+    e1.record(stream)
+    e1.synchronize()
+    final_ms = e0.elapsed_time(e1)
+    del stores, acc, mean, std
+    torch.cuda.empty_cache()
+    copy_gbs = copy_bandwidth(torch)
+
+    head = variants[0]
+    r0 = res[head]
+    bpl = BYTES_PER_LUP[head]
+    out = {
+        "metric": METRIC, "value": round(r0["value"], 4), "unit": "GLUPS", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(r0["ms_per_step"], 3), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64" if head == "fp64" else "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": f"c5: Mach-2000 jet, the 5056x2528 level with its 2528x1264 partner on the same "
+                               f"seeds (domain [0,1]x[-0.25,0.25], t_final={t_final:g}), M={C5_M_TOTAL} "
+                               f"streamed in batches of {B}; one step = {L} step launches of both levels "
+                               f"on one batch + its restriction to 2528x1264, Chan merge, scatter into the "
+                               f"M={C5_M_TOTAL} sample stores, per-cell sort and W1 between the levels, {head}",
+                   "precision": head, "levels": [[w.nx, w.ny] for w in works], "batch": B,
+                   "realizations_total": C5_M_TOTAL, "launches_per_step": L, "t_final": t_final,
+                   "seed": inputs.DEFAULT_SEED, "time_steps_reached": r0["steps"],
+                   "t_reached": r0["t_reached"],
+                   "node_updates_per_launch": B * lup_per_launch_per_real,
+                   "step_kernel_rows_per_wave": r0["tuned"],
+                   "phases_ms_per_step": r0["phases_ms"],
+                   "once_per_job_sort_and_w1_of_the_full_stores_ms": round(final_ms, 1)},
+        "roofline": {"bound": "hbm", "achieved": round(r0["achieved"], 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(r0["achieved"] / HBM_PEAK_GBS, 4),
+                     "traffic": measured_traffic(head, "c5"),
+                     "kernel": "vlbm step kernel (both levels per launch)", "bytes_per_node_update": bpl,
+                     "avg_launch_ms": round(r0["avg_launch_ms"], 4),
+                     "device_copy_GBs": round(copy_gbs, 1),
+                     "frac_of_device_copy": round(r0["achieved"] / copy_gbs, 4)},
+        "w1_between_levels_batch": r0["w1_between_levels"],
+    }
+    if "mixed" in res and head == "fp64":
+        rm = res["mixed"]
+        out["mixed"] = {
+            "value": round(rm["value"], 4), "unit": "GLUPS", "dtype": "f32+f64",
+            "ms_per_step": round(rm["ms_per_step"], 3),
+            "speedup_vs_fp64": round(rm["value"] / r0["value"], 4),
+            "roofline": {"bound": "hbm", "achieved": round(rm["achieved"], 1), "peak": HBM_PEAK_GBS,
+                         "unit": "GB/s", "frac": round(rm["achieved"] / HBM_PEAK_GBS, 4),
+                         "traffic": measured_traffic("mixed", "c5"),
+                         "bytes_per_node_update": BYTES_PER_LUP["mixed"],
+                         "avg_launch_ms": round(rm["avg_launch_ms"], 4),
+                         "frac_of_device_copy": round(rm["achieved"] / copy_gbs, 4)},
+            "time_steps_reached": rm["steps"], "step_kernel_rows_per_wave": rm["tuned"],
+            "phases_ms_per_step": rm["phases_ms"],
+        }
+        if not args.no_mixed_error:
+            out["mixed"]["error_vs_fp64"] = mixed_error_study(torch, vlbm, inputs, inputs.WORKLOADS["jet640"],
+                                                              (0.01, 0.1, 1.0), 240)
+    for key in ("roofline",):
+        tr = out[key].get("traffic")
+        if tr:
+            per_lup = tr / (B * lup_per_launch_per_real)
+            out[key]["hbm_bytes_per_node_update"] = round(per_lup, 1)
+            out[key]["hbm_GBs_implied"] = round(out[key]["achieved"] * per_lup / bpl, 1)
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(fine.name, fine.nx, fine.ny, fine.dx, fine.y_min, steps=3)
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+def run_pass(args, torch, vlbm, inputs) -> int:
+    """Single-level workload, one benchmark step = one whole pass to t_final."""
+    import numpy as np
+
     w = inputs.WORKLOADS[args.workload]
     R, r_stats, r_w1 = w.m, 1, 2
     coefs = inputs.kl_coefficients(inputs.DEFAULT_SEED, 0, R)
@@ -182,15 +524,6 @@ def main() -> int:
         lv = vlbm.Level(w.nx, w.ny, w.dx, w.y_min,
                         (vlbm._VP * 2)(bufs[0].data_ptr(), bufs[1].data_ptr()))
         return lv, bufs
-
-    if args.study:
-        return run_study(args, torch, vlbm, inputs)
-    if args.c5:
-        return run_c5(args, torch, vlbm, inputs)
-    if args.w12:
-        return run_w12(args, torch, vlbm)
-    if args.centerline:
-        return run_centerline(args, torch, vlbm, inputs)
 
     if args.profile_launches > 0:
         params = vlbm.Params.jet(precision=args.precision if args.precision != "both" else "fp64")
@@ -427,7 +760,7 @@ def main() -> int:
         }
         add_hbm(out["mixed"]["roofline"], "mixed")
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(w)
+        out["cpu_baseline"] = cpu_baseline(w.name, w.nx, w.ny, w.dx, w.y_min)
     print(json.dumps(out), flush=True)
     return 0
 
