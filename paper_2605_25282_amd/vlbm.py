@@ -226,6 +226,14 @@ def vlbm_ensemble_stats(h, level: int, r: int, acc, n_prev: int, samples=None,
                                      _f64(samples, rows * cells, "samples"), rows, m_offset))
 
 
+def vlbm_stats_finalize(acc, n_cells: int, n_total: int, mean=None, std=None, stream=None) -> None:
+    """acc: float64 [3][2][n_cells] of n_total realizations; mean, std: float64
+    [3][n_cells] (either may be None)."""
+    _check(lib().vlbm_stats_finalize(_f64(acc, 6 * n_cells, "acc"), n_cells, n_total,
+                                     _f64(mean, 3 * n_cells, "mean"), _f64(std, 3 * n_cells, "std"),
+                                     _stream(stream)))
+
+
 def vlbm_kl_coefficients(seed: int, first: int, count: int, modes: int = 10) -> np.ndarray:
     """KL coefficients of realizations first .. first+count-1, shape (count, 2 modes)."""
     out = np.zeros((count, 2 * modes))

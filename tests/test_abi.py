@@ -26,6 +26,18 @@ def test_library_exports_every_declared_symbol(lib):
     assert not missing, missing
 
 
+def test_binding_wraps_every_declared_function(lib):
+    """The Python binding carries every declared function under the same name
+    (with the signature table entry the loader sets), so a caller never reaches
+    an unwrapped entry point; vlbm_last_error is wrapped as last_error."""
+    import inspect
+    src = inspect.getsource(vlbm.lib)
+    for n in vlbm.header_functions():
+        assert f'"{n}"' in src, f"{n} has no signature entry"
+        if n != "vlbm_last_error":
+            assert callable(getattr(vlbm, n, None)), f"{n} has no wrapper"
+
+
 def _slots(nx, periodic=False):
     """Element slots of a plane row: 64 per strip of 60 columns (a bounded level
     of 60 q + 1 columns keeps q strips, the last one carrying 61 columns)."""
