@@ -248,7 +248,12 @@ def test_paper_domain_observables_500_vs_1000():
         "E_std": O.cell_mean_abs_diff(O.ensemble_std(rho[0]), O.ensemble_std(rho[1])),
         "E_strong": O.strong_error(rho[0], rho[1]),
     }
+    # W_{1,2}: each pair's exact assignment is optimal up to the rounding of the
+    # Hungarian potentials, which carry the size of the largest cost of the pair
+    # (density differences of order 1), so a near-tie may pick the other
+    # assignment: at most ~m * eps * 5 = 5e-15 apart per pair, and on average.
+    abs_tol = {"W12": 1e-14}
     for name, val in ref.items():
         got = st.errors[("cauchy", name)][0]
-        print(f"{name}: gpu {got:.10g} oracle {val:.10g}")
-        assert val > 0 and got == pytest.approx(val, rel=1e-10), name
+        print(f"{name}: gpu {got:.10g} oracle {val:.10g} (diff {abs(got - val):.2e})")
+        assert val > 0 and got == pytest.approx(val, rel=1e-10, abs=abs_tol.get(name, 0.0)), name
