@@ -265,6 +265,24 @@ vlbm_status vlbm_sort_samples(double *samples, int64_t n_cells, int32_t m, void 
 vlbm_status vlbm_w1(const double *sorted_a, const double *sorted_b, int64_t n_cells, int32_t m,
                     double *w1_cell, double *w1_mean, void *hip_stream);
 
+/*
+ * vlbm_w1 without any device allocation, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc).  Same arguments, kernels and results (bit for bit)
+ * as vlbm_w1; the partial sums of the W_{1,1} average live in a fixed
+ * workspace compiled into the library, one copy per device, held until the
+ * process ends.  Limit: with w1_mean non-NULL, n_cells <=
+ * VLBM_W1_NOALLOC_MAX_PARTIALS * 1024 (16 777 216 cells, 128 KiB of
+ * workspace); larger inputs return VLBM_ERR_SIZE before anything is enqueued.
+ * Every call on a device shares that device's workspace: calls that overlap
+ * in time on one device (different streams, or threads without ordering)
+ * race and must be serialized by the caller.  Calls ordered on one stream are
+ * safe.  Enqueued on hip_stream.
+ */
+#define VLBM_W1_NOALLOC_MAX_PARTIALS 16384
+vlbm_status vlbm_w1_noalloc(const double *sorted_a, const double *sorted_b, int64_t n_cells, int32_t m,
+                            double *w1_cell, double *w1_mean, void *hip_stream);
+
 /* ---------------------------------------------------------------------------
  * Observables of the convergence study (Sec. 3.3-3.4) and quantile diagnostics
  * (Sec. 4).  Sample stores are laid out [m realizations][n_cells] as written by

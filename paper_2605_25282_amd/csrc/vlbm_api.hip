@@ -824,6 +824,69 @@ vlbm_status vlbm_w1(const double *a, const double *b, int64_t n_cells, int32_t m
     return VLBM_OK;
 }
 
+} // extern "C"
+
+// Workspace of vlbm_w1_noalloc: the stage-1 partial sums of the W_{1,1}
+// average, in a file-scope device array (one copy per device, held until the
+// process ends).  Host code never passes the array's name to a kernel: its
+// device address is looked up once per device and kept in g_noalloc_ptr.
+static __device__ __align__(256) double scratch[VLBM_W1_NOALLOC_MAX_PARTIALS];
+
+namespace {
+constexpr int NOALLOC_MAX_DEVICES = 64;
+double *g_noalloc_ptr[NOALLOC_MAX_DEVICES] = {};
+std::mutex g_noalloc_mu;
+
+// Device address of the current device's copy of the workspace (looked up on
+// the first call made with that device current).
+vlbm_status noalloc_scratch(double **out)
+{
+    int dev = -1;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= NOALLOC_MAX_DEVICES)
+        return fail(VLBM_ERR_ARG, "device ordinal %d outside [0, %d)", dev, NOALLOC_MAX_DEVICES);
+    std::lock_guard<std::mutex> lk(g_noalloc_mu);
+    if (!g_noalloc_ptr[dev]) {
+        void *ptr = nullptr;
+        const hipError_t he = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (he != hipSuccess || !ptr)
+            return fail(VLBM_ERR_HIP, "hipGetSymbolAddress(scratch) on device %d failed: %s", dev,
+                        hipGetErrorString(he));
+        g_noalloc_ptr[dev] = (double *)ptr;
+    }
+    *out = g_noalloc_ptr[dev];
+    return VLBM_OK;
+}
+} // namespace
+
+extern "C" {
+
+vlbm_status vlbm_w1_noalloc(const double *a, const double *b, int64_t n_cells, int32_t m, double *w1_cell,
+                            double *w1_mean, void *hip_stream)
+{
+    vlbm_status rc = check_w1_args(a, b, n_cells, m);
+    if (rc != VLBM_OK)
+        return rc;
+    if (w1_mean && reduction_partials(n_cells) > VLBM_W1_NOALLOC_MAX_PARTIALS)
+        return fail(VLBM_ERR_SIZE, "vlbm_w1_noalloc: n_cells = %lld needs %lld partial sums, the fixed "
+                    "workspace holds %d (at most %lld cells with w1_mean)", (long long)n_cells,
+                    reduction_partials(n_cells), VLBM_W1_NOALLOC_MAX_PARTIALS,
+                    (long long)VLBM_W1_NOALLOC_MAX_PARTIALS * 1024LL);
+    if (!w1_cell && !w1_mean)
+        return VLBM_OK;
+    double *ws = nullptr;
+    if (w1_mean) {
+        rc = noalloc_scratch(&ws);
+        if (rc != VLBM_OK)
+            return rc;
+    }
+    // every partial the second stage reads is written by the first, so the
+    // workspace needs no clearing between calls
+    launch_w1(a, b, n_cells, m, w1_cell, w1_mean, ws, (hipStream_t)hip_stream);
+    LAUNCH_CHECK("w1_noalloc");
+    return VLBM_OK;
+}
+
 vlbm_status vlbm_strong_error(const double *a, const double *b, int64_t n_cells, int32_t m, double *per_real,
                               double *out, void *hip_stream)
 {

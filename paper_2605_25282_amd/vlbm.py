@@ -97,6 +97,7 @@ def lib():
             "vlbm_stats_finalize": ([_VP, i64, i64, _VP, _VP, _VP], i32),
             "vlbm_sort_samples": ([_VP, i64, i32, _VP], i32),
             "vlbm_w1": ([_VP, _VP, i64, i32, _VP, _VP, _VP], i32),
+            "vlbm_w1_noalloc": ([_VP, _VP, i64, i32, _VP, _VP, _VP], i32),
             "vlbm_strong_error": ([_VP, _VP, i64, i32, _VP, _VP, _VP], i32),
             "vlbm_mean_abs_diff": ([_VP, _VP, i64, _VP, _VP], i32),
             "vlbm_quantiles": ([_VP, i64, i32, ctypes.POINTER(i32), i32, _VP, _VP], i32),
@@ -250,6 +251,13 @@ def vlbm_w1(a, b, n_cells: int, m: int, w1_cell=None, w1_mean=None, stream=None)
     _check(lib().vlbm_w1(_f64(a, n_cells * m, "a"), _f64(b, n_cells * m, "b"), n_cells, m,
                          _f64(w1_cell, n_cells, "w1_cell"), _f64(w1_mean, 1, "w1_mean"),
                          _stream(stream)))
+
+
+def vlbm_w1_noalloc(a, b, n_cells: int, m: int, w1_cell=None, w1_mean=None, stream=None) -> None:
+    """vlbm_w1 with the library's fixed per-device workspace (no device allocation)."""
+    _check(lib().vlbm_w1_noalloc(_f64(a, n_cells * m, "a"), _f64(b, n_cells * m, "b"), n_cells, m,
+                                 _f64(w1_cell, n_cells, "w1_cell"), _f64(w1_mean, 1, "w1_mean"),
+                                 _stream(stream)))
 
 
 def vlbm_strong_error(a, b, n_cells: int, m: int, per_real, out, stream=None) -> None:

@@ -172,6 +172,12 @@ def test_observable_entry_points_validate_before_launch(lib):
     assert lib.vlbm_width_ratio(fake, 10, 0, fake, None) == vlbm.ERR_SIZE
     assert lib.vlbm_w1(fake, fake, 0, 4, None, fake, None) == vlbm.ERR_SIZE
     assert lib.vlbm_w1(fake, fake, 10, 0, fake, fake, None) == vlbm.ERR_SIZE
+    assert lib.vlbm_w1_noalloc(None, fake, 10, 4, fake, fake, None) == vlbm.ERR_ARG
+    assert lib.vlbm_w1_noalloc(fake, fake, 0, 4, None, fake, None) == vlbm.ERR_SIZE
+    # the fixed workspace holds VLBM_W1_NOALLOC_MAX_PARTIALS partial sums of 1024 cells
+    limit = 16384 * 1024
+    assert lib.vlbm_w1_noalloc(fake, fake, limit + 1, 4, None, fake, None) == vlbm.ERR_SIZE
+    assert "16384" in vlbm.last_error()
     assert lib.vlbm_w12(None, fake, 10, 10, 4, 3, fake, None, None) == vlbm.ERR_ARG
     assert lib.vlbm_w12(fake, fake, 10, 10, 4, 3, None, None, None) == vlbm.ERR_ARG
     assert lib.vlbm_w12(fake, fake, 10, 10, 1025, 3, fake, None, None) == vlbm.ERR_SIZE
