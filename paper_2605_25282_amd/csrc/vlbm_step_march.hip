@@ -145,7 +145,21 @@ __device__ __forceinline__ void march_item(const PhysArgs &ph, const LevelArgs &
     // the unused slots -- and every store instruction writes whole lines.
     const unsigned slot_in = col_slot(cx, L.nstrip);
     const unsigned slot_out = (unsigned)(SLOTS * strip + ((lane - 2) & (SLOTS - 1)));
-    auto col_in = [&](int v, int sl) -> unsigned { return slot_in * St::esize(v, sl); };
+    // The halo lanes need the macroscopic state (radius-2 stencil) but only two
+    // population values: u_1 of lane 1 (the west face of the strip) and u_2 of
+    // lane 62 (its east face).  For the other population planes a halo lane reads
+    // the slot of the nearest output column instead, a line the wave reads anyway,
+    // so the neighbouring strips' lines are fetched for 8 of the 20 planes only.
+    // Whatever a halo lane computes from those values never reaches an output lane.
+    const unsigned slot_inner = (unsigned)__shfl((int)slot_in, lane < 2 ? 2 : 61, 64);
+    const bool halo_lane = lane < 2 || lane > 61;
+    unsigned slot_pop[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const bool needed = !halo_lane || (q == 0 && lane == 1) || (q == 1 && lane == 62);
+        slot_pop[q] = needed ? slot_in : slot_inner;
+    }
+    auto col_in = [&](int v, int sl) -> unsigned { return (sl == 0 ? slot_in : slot_pop[sl - 1]) * St::esize(v, sl); };
     auto col_out = [&](int v, int sl) -> unsigned { return slot_out * St::esize(v, sl); };
     double wmax = 0.0;
     int bad = 0;
