@@ -252,22 +252,24 @@ def stat_errors(torch, vlbm, a, b, ncell_w1, R):
 def mixed_error_study(torch, vlbm, inputs, w, fracs, chunk):
     """Ensemble statistics of the mixed variant against an FP64 ensemble of the
     same seeds at t = frac * t_final, next to two references for the size of such
-    differences: the round-off floor (an FP64 ensemble of the same seeds whose
-    inlet densities are moved up by one ulp, which the Dirichlet inlet keeps
-    feeding in) and the sampling floor (an FP64 ensemble on the next M seeds).
-    Statistics: mean and std of (rho, |v|, p) on the nodes, W1 of the 2 x 2
-    restricted density."""
+    differences: the round-off floor (FP64 ensembles of the same seeds whose
+    inlet density, or inlet energy, is moved by one ulp up or down, which the
+    Dirichlet inlet keeps feeding in: four perturbations, their spread and
+    maximum reported) and the sampling floor (an FP64 ensemble on the next M
+    seeds).  Statistics: mean and std of (rho, |v|, p) on the nodes, W1 of the
+    2 x 2 restricted density."""
     R, r_w1 = w.m, 2
     ncell, ncell_w1 = w.nx * w.ny, (w.nx // r_w1) * (w.ny // r_w1)
     dev = dict(dtype=torch.float64, device="cuda")
 
-    def run(precision, t_end, first_seed=0, ulp=False):
+    def run(precision, t_end, first_seed=0, ulp=None):
         coefs = inputs.kl_coefficients(inputs.DEFAULT_SEED, first_seed, R)
         ens = vlbm.Ensemble(vlbm.Params.jet(precision=precision), [(w.nx, w.ny, w.dx, w.y_min)], coefs, R)
-        if ulp:
+        if ulp is not None:  # (variable, direction): one ulp on the inlet column's u
+            var, sign = ulp
             st = ens.state(0)  # [4 var][5 slot][R][ny][nx]
-            col = st[0, 0, :, :, 0]
-            st[0, 0, :, :, 0] = torch.nextafter(col, torch.full_like(col, float("inf")))
+            col = st[var, 0, :, :, 0]
+            st[var, 0, :, :, 0] = torch.nextafter(col, torch.full_like(col, sign * float("inf")))
             t, s, a, _ = ens.times(0)
             ens.set_state(0, st, t, s, a)
             del st
@@ -290,10 +292,22 @@ def mixed_error_study(torch, vlbm, inputs, w, fracs, chunk):
     for frac in fracs:
         t_e = w.t_final * frac
         ref = run("fp64", t_e)
+        mixed = stat_errors(torch, vlbm, ref, run("mixed", t_e), ncell_w1, R)
+        floors = {f"{name}{'+' if sign > 0 else '-'}1ulp": stat_errors(torch, vlbm, ref,
+                                                                       run("fp64", t_e, ulp=(var, sign)),
+                                                                       ncell_w1, R)
+                  for name, var in (("rho", 0), ("E", 3)) for sign in (1, -1)}
+        worst = {"w1_over_mean_rho": max(f["w1_over_mean_rho"] for f in floors.values()),
+                 "mean_rel_l1": [max(f["mean_rel_l1"][k] for f in floors.values()) for k in range(3)],
+                 "std_rel_l1": [max(f["std_rel_l1"][k] for f in floors.values()) for k in range(3)]}
         row = {"t": t_e, "time_steps_per_realization": ref["steps"],
-               "mixed_vs_fp64": stat_errors(torch, vlbm, ref, run("mixed", t_e), ncell_w1, R),
-               "fp64_one_ulp_inlet_vs_fp64": stat_errors(torch, vlbm, ref, run("fp64", t_e, ulp=True),
-                                                         ncell_w1, R),
+               "mixed_vs_fp64": mixed,
+               "fp64_one_ulp_inlet_vs_fp64": floors,
+               "roundoff_floor_max": worst,
+               "mixed_over_floor_max": {
+                   "w1": round(mixed["w1_over_mean_rho"] / worst["w1_over_mean_rho"], 3),
+                   "mean": [round(mixed["mean_rel_l1"][k] / worst["mean_rel_l1"][k], 3) for k in range(3)],
+                   "std": [round(mixed["std_rel_l1"][k] / worst["std_rel_l1"][k], 3) for k in range(3)]},
                "fp64_independent_seeds_vs_fp64": stat_errors(torch, vlbm, ref, run("fp64", t_e, first_seed=R),
                                                              ncell_w1, R)}
         out.append(row)
@@ -341,9 +355,13 @@ def run_headline(args, torch, vlbm, inputs) -> int:
             ens.tune("march", args.chunk_rows)
         ens.step(t_final, args.profile_launches, want_done=True)
         ens.close()
+        # a plain 2 GiB device copy: what FETCH_SIZE / WRITE_SIZE read for bytes of known size
+        a = torch.ones(1 << 28, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        b.copy_(a)
         torch.cuda.synchronize()
         print(f"profiled {args.profile_launches} step launches of the 5056x2528 + 2528x1264 pair, "
-              f"{B} realizations, {prec}", flush=True)
+              f"{B} realizations, {prec}, and one 2 GiB copy", flush=True)
         return 0
 
     # the job's statistics: running accumulators and the sample stores of all M realizations
@@ -365,12 +383,15 @@ def run_headline(args, torch, vlbm, inputs) -> int:
         params = vlbm.Params.jet(precision=prec)
         coefs = vlbm.vlbm_kl_coefficients(inputs.DEFAULT_SEED, 0, B)
         ens = vlbm.Ensemble(params, levels, coefs, B)
-        tuned = None
         if not args.no_tune:
-            tuned = ens.autotune(t_final, 4)  # live steps, counted toward t_final
-            progress(f"{prec}: autotuned rows per wave {tuned}")
+            ens.autotune(t_final, 8)  # live steps, counted toward t_final
         elif args.chunk_rows:
             ens.tune("march", args.chunk_rows)
+        chunks, wpb, order = ens.get_tuning()
+        tuned = {"rows_per_wave": chunks, "waves_per_block": wpb,
+                 "item_order": "strip fastest" if order == 0 else "realization fastest",
+                 "autotuned": not args.no_tune}
+        progress(f"{prec}: step kernel decomposition {tuned}")
         acc_step = {"step_ms": 0.0, "stats_s": 0.0}
 
         def one_step(k, timed):
@@ -465,7 +486,7 @@ def run_headline(args, torch, vlbm, inputs) -> int:
                    "seed": inputs.DEFAULT_SEED, "time_steps_reached": r0["steps"],
                    "t_reached": r0["t_reached"],
                    "node_updates_per_launch": B * lup_per_launch_per_real,
-                   "step_kernel_rows_per_wave": r0["tuned"],
+                   "step_kernel_decomposition": r0["tuned"],
                    "phases_ms_per_step": r0["phases_ms"],
                    "once_per_job_sort_and_w1_of_the_full_stores_ms": round(final_ms, 1)},
         "roofline": {"bound": "hbm", "achieved": round(r0["achieved"], 1), "peak": HBM_PEAK_GBS,
@@ -489,7 +510,7 @@ def run_headline(args, torch, vlbm, inputs) -> int:
                          "bytes_per_node_update": BYTES_PER_LUP["mixed"],
                          "avg_launch_ms": round(rm["avg_launch_ms"], 4),
                          "frac_of_device_copy": round(rm["achieved"] / copy_gbs, 4)},
-            "time_steps_reached": rm["steps"], "step_kernel_rows_per_wave": rm["tuned"],
+            "time_steps_reached": rm["steps"], "step_kernel_decomposition": rm["tuned"],
             "phases_ms_per_step": rm["phases_ms"],
         }
         if not args.no_mixed_error:

@@ -159,7 +159,9 @@ struct vlbm_ensemble {
     int kernel = VLBM_KERNEL_MARCH;
     int chunk_rows = 0;     // 0 = automatic
     int n_cu = 256;         // compute units of the device
-    int march_blocks_per_cu = 1;
+    int march_blocks_per_cu[3] = {4, 2, 1}; // resident blocks per CU for 1, 2, 4 waves per block
+    int waves_per_block = 4; // wavefronts per block of the marching kernel (1, 2 or 4)
+    int item_order = 0;      // 0 strip fastest, 1 realization fastest
     std::vector<int> level_chunk; // per-level chunk override (0 = from chunk_rows / model)
     // hipGraph of GRAPH_STEPS consecutive steps (ring phases 0,1,2,...), captured on
     // an internal stream and replayed on the ensemble's stream
@@ -172,15 +174,29 @@ struct vlbm_ensemble {
 static constexpr int GRAPH_STEPS = 30; // a multiple of 3 (the control ring's period)
 
 namespace {
-// Process-wide cache of tuned chunk heights.
-typedef std::tuple<int, int, int, int, int, int> TuneKey; // nx, ny, R, precision, bc, limiter
-std::map<TuneKey, int> g_tune_cache;
+// Process-wide cache of tuned configurations, keyed by the whole launch
+// (precision, boundary mode, limiter, realizations and every level's shape):
+// the chunk height of each level, waves per block and item order.
+typedef std::vector<long long> TuneKey;
+struct TuneChoice {
+    std::vector<int> chunks;
+    int waves_per_block = 4;
+    int item_order = 0;
+};
+std::map<TuneKey, TuneChoice> g_tune_cache;
 std::mutex g_tune_mu;
 
-TuneKey tune_key(const vlbm_ensemble *e, const LevelArgs &L)
+TuneKey tune_key(const vlbm_ensemble *e)
 {
-    return TuneKey(L.nx, L.ny, L.R, e->p.precision, e->p.bc, e->p.limiter);
+    TuneKey k{e->p.precision, e->p.bc, e->p.limiter, e->n_real, (long long)e->levels.size()};
+    for (const LevelArgs &L : e->levels) {
+        k.push_back(L.nx);
+        k.push_back(L.ny);
+    }
+    return k;
 }
+
+int wpb_index(int wpb) { return wpb == 1 ? 0 : (wpb == 2 ? 1 : 2); }
 } // namespace
 
 namespace {
@@ -196,10 +212,17 @@ int strips_of(const vlbm_ensemble *e, const LevelArgs &L, int *lane62)
     return L.nstrip;
 }
 
+// Resident wavefronts of the marching kernel (one per SIMD at its register use).
+long long resident_waves(const vlbm_ensemble *e)
+{
+    const int wpb = e->waves_per_block;
+    return (long long)e->n_cu * e->march_blocks_per_cu[wpb_index(wpb)] * wpb;
+}
+
 // Default chunk height: about twelve work items per resident wave, rows >= 16.
 int model_chunk(const vlbm_ensemble *e, const LevelArgs &L, int nstrip)
 {
-    const long long target = 12LL * e->n_cu * 4 * e->march_blocks_per_cu;
+    const long long target = 12LL * resident_waves(e);
     const long long per_chunk = (long long)L.R * nstrip;
     long long nch = (target + per_chunk - 1) / per_chunk;
     if (nch < 1)
@@ -222,6 +245,7 @@ MarchArgs march_args(const vlbm_ensemble *e, int level)
         chunk = L.ny;
     ma.chunk = chunk;
     ma.nchunk = (L.ny + chunk - 1) / chunk;
+    ma.order = e->item_order;
     return ma;
 }
 
@@ -237,8 +261,10 @@ MultiLevel multi_level(const vlbm_ensemble *e, int l0, int l1, unsigned *grid)
         ml.ma[i] = march_args(e, l0 + i);
         ml.item_off[i + 1] = ml.item_off[i] + (long long)ml.L[i].R * ml.ma[i].nstrip * ml.ma[i].nchunk;
     }
-    long long blocks = (ml.item_off[ml.nlev] + 3) / 4;
-    const long long resident = (long long)e->n_cu * e->march_blocks_per_cu;
+    const int wpb = e->waves_per_block;
+    ml.wpb = wpb;
+    long long blocks = (ml.item_off[ml.nlev] + wpb - 1) / wpb;
+    const long long resident = resident_waves(e) / wpb;
     if (blocks > resident)
         blocks = resident;
     if (blocks < 1)
@@ -264,10 +290,11 @@ vlbm_status launch_step(vlbm_ensemble *e, const PhysArgs &ph, int l0, int l1, in
     } else {
         unsigned grid = 0;
         const MultiLevel ml = multi_level(e, l0, l1, &grid);
+        const unsigned threads = 64u * (unsigned)ml.wpb;
         if (e->p.precision == VLBM_FP64)
-            step_march_kernel<0><<<grid, 256, 0, st>>>(ph, ml, e->ctl, phase, t_final);
+            step_march_kernel<0><<<grid, threads, 0, st>>>(ph, ml, e->ctl, phase, t_final);
         else
-            step_march_kernel<1><<<grid, 256, 0, st>>>(ph, ml, e->ctl, phase, t_final);
+            step_march_kernel<1><<<grid, threads, 0, st>>>(ph, ml, e->ctl, phase, t_final);
     }
     LAUNCH_CHECK("step");
     return VLBM_OK;
@@ -420,12 +447,15 @@ vlbm_status vlbm_init_ensemble(const vlbm_params *p, const vlbm_level *levels, i
         if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess &&
             prop.multiProcessorCount > 0)
             e->n_cu = prop.multiProcessorCount;
-        int occ = 0;
-        hipError_t oe = p->precision == VLBM_FP64
-                            ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, step_march_kernel<0>, 256, 0)
-                            : hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, step_march_kernel<1>, 256, 0);
-        if (oe == hipSuccess && occ > 0)
-            e->march_blocks_per_cu = occ;
+        for (int i = 0; i < 3; ++i) {
+            const int threads = 64 << i;
+            int occ = 0;
+            hipError_t oe = p->precision == VLBM_FP64
+                                ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, step_march_kernel<0>, threads, 0)
+                                : hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, step_march_kernel<1>, threads, 0);
+            if (oe == hipSuccess && occ > 0)
+                e->march_blocks_per_cu[i] = occ;
+        }
     }
     const PhysArgs ph = phys_args(*p);
     for (const LevelArgs &L : e->levels) {
@@ -442,14 +472,15 @@ vlbm_status vlbm_init_ensemble(const vlbm_params *p, const vlbm_level *levels, i
             return fail(VLBM_ERR_HIP, "init launch failed: %s", hipGetErrorString(le));
         }
     }
-    // Chunk heights tuned earlier in this process for the same shapes.
+    // A configuration tuned earlier in this process for the same launch.
     e->level_chunk.assign(e->levels.size(), 0);
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
-        for (size_t l = 0; l < e->levels.size(); ++l) {
-            auto it = g_tune_cache.find(tune_key(e, e->levels[l]));
-            if (it != g_tune_cache.end())
-                e->level_chunk[l] = it->second;
+        auto it = g_tune_cache.find(tune_key(e));
+        if (it != g_tune_cache.end()) {
+            e->level_chunk = it->second.chunks;
+            e->waves_per_block = it->second.waves_per_block;
+            e->item_order = it->second.item_order;
         }
     }
     // The host coefficient array may be released once this call returns.
@@ -999,9 +1030,108 @@ vlbm_status vlbm_tune(vlbm_ensemble *e, int32_t kernel, int32_t chunk_rows)
     e->chunk_rows = chunk_rows;
     e->use_graph = !no_graph;
     std::fill(e->level_chunk.begin(), e->level_chunk.end(), 0);
+    e->waves_per_block = 4;
+    e->item_order = 0;
     drop_graph(e);
     return VLBM_OK;
 }
+
+vlbm_status vlbm_set_tuning(vlbm_ensemble *e, const int32_t *chunks, int32_t waves_per_block, int32_t item_order)
+{
+    if (!e)
+        return fail(VLBM_ERR_ARG, "ensemble is NULL");
+    if (waves_per_block != 1 && waves_per_block != 2 && waves_per_block != 4)
+        return fail(VLBM_ERR_ARG, "waves_per_block must be 1, 2 or 4 (got %d)", waves_per_block);
+    if (item_order != 0 && item_order != 1)
+        return fail(VLBM_ERR_ARG, "item_order must be 0 or 1 (got %d)", item_order);
+    if (chunks)
+        for (size_t l = 0; l < e->levels.size(); ++l)
+            if (chunks[l] != 0 && (chunks[l] < 4 || chunks[l] > 65536))
+                return fail(VLBM_ERR_ARG, "chunks[%zu] must be 0 or lie in [4, 65536] (got %d)", l, chunks[l]);
+    for (size_t l = 0; l < e->levels.size(); ++l)
+        e->level_chunk[l] = chunks ? chunks[l] : 0;
+    e->waves_per_block = waves_per_block;
+    e->item_order = item_order;
+    drop_graph(e);
+    return VLBM_OK;
+}
+
+vlbm_status vlbm_get_tuning(const vlbm_ensemble *e, int32_t *chunks, int32_t *waves_per_block, int32_t *item_order)
+{
+    if (!e)
+        return fail(VLBM_ERR_ARG, "ensemble is NULL");
+    if (chunks)
+        for (size_t l = 0; l < e->levels.size(); ++l)
+            chunks[l] = march_args(e, (int)l).chunk;
+    if (waves_per_block)
+        *waves_per_block = e->waves_per_block;
+    if (item_order)
+        *item_order = e->item_order;
+    return VLBM_OK;
+}
+
+namespace {
+// Work model of one launch under the static round-robin dealing: every work
+// item costs its rows plus the 4-row prologue of the march, item i goes to
+// wave i mod W, and the launch lasts as long as the most loaded wave.
+double dealing_model(const vlbm_ensemble *e, const std::vector<int> &chunks)
+{
+    const long long W = resident_waves(e);
+    std::vector<double> load((size_t)W, 0.0);
+    long long i = 0;
+    for (size_t l = 0; l < e->levels.size(); ++l) {
+        const LevelArgs &L = e->levels[l];
+        int lane62 = 0;
+        const int nstrip = strips_of(e, L, &lane62);
+        const int chunk = std::min(chunks[l], L.ny);
+        const int nchunk = (L.ny + chunk - 1) / chunk;
+        const long long per_real = (long long)nstrip * nchunk;
+        const long long n = (long long)L.R * per_real;
+        for (long long k = 0; k < n; ++k, ++i) {
+            const long long rem = e->item_order == 0 ? k % per_real : k / L.R;
+            const int ch = (int)(rem / nstrip);
+            const int rows = std::min(chunk, L.ny - ch * chunk);
+            load[(size_t)(i % W)] += rows + 4;
+        }
+    }
+    return *std::max_element(load.begin(), load.end());
+}
+
+// Candidate chunk tuples: for every common target height h (the distinct heights
+// ny_l / n of all levels), each level takes the height of its even split closest
+// above h; tuples are ranked by the dealing model and the best `keep` returned.
+std::vector<std::vector<int>> chunk_candidates(const vlbm_ensemble *e, size_t keep)
+{
+    std::vector<int> targets;
+    for (const LevelArgs &L : e->levels)
+        for (int n = 1; n <= std::min(L.ny, 256); ++n) {
+            const int h = std::max(4, (L.ny + n - 1) / n);
+            if (std::find(targets.begin(), targets.end(), h) == targets.end())
+                targets.push_back(h);
+        }
+    std::vector<std::pair<double, std::vector<int>>> ranked;
+    for (int h : targets) {
+        std::vector<int> t;
+        for (const LevelArgs &L : e->levels) {
+            const int n = std::max(1, L.ny / h);
+            t.push_back(std::max(4, (L.ny + n - 1) / n));
+        }
+        bool seen = false;
+        for (auto &r : ranked)
+            seen = seen || r.second == t;
+        if (!seen)
+            ranked.push_back({dealing_model(e, t), t});
+    }
+    std::stable_sort(ranked.begin(), ranked.end(),
+                     [](const std::pair<double, std::vector<int>> &a, const std::pair<double, std::vector<int>> &b) {
+                         return a.first < b.first;
+                     });
+    std::vector<std::vector<int>> out;
+    for (size_t k = 0; k < ranked.size() && out.size() < keep; ++k)
+        out.push_back(ranked[k].second);
+    return out;
+}
+} // namespace
 
 vlbm_status vlbm_autotune(vlbm_ensemble *e, double t_final, int32_t steps_per_candidate, int32_t *chunks_out)
 {
@@ -1012,106 +1142,107 @@ vlbm_status vlbm_autotune(vlbm_ensemble *e, double t_final, int32_t steps_per_ca
     if (steps_per_candidate < 1 || steps_per_candidate > 1000)
         return fail(VLBM_ERR_ARG, "steps_per_candidate must lie in [1, 1000]");
     const int nlev = (int)e->levels.size();
-    if (e->kernel != VLBM_KERNEL_MARCH) {
+    auto report = [&]() {
         if (chunks_out)
             for (int l = 0; l < nlev; ++l)
-                chunks_out[l] = 0;
+                chunks_out[l] = e->kernel == VLBM_KERNEL_MARCH ? march_args(e, l).chunk : 0;
+    };
+    if (e->kernel != VLBM_KERNEL_MARCH) {
+        report();
         return VLBM_OK;
     }
     drop_graph(e);
-    // Candidates per level, ranked by the work model.
-    const int max_cand = 6;
-    std::vector<std::vector<int>> cand(nlev);
-    const long long waves = (long long)e->n_cu * 4 * e->march_blocks_per_cu;
+    // A configuration is (chunk height per level, waves per block, item order),
+    // timed on steps_per_candidate live steps of the whole launch (all levels, as
+    // vlbm_step runs them).  Search: the chunk tuples first (4 waves per block,
+    // strip-fastest order), ranked by the dealing model, then the block size and
+    // the item order around the fastest tuple.
+    std::vector<int> dflt(nlev);
+    e->waves_per_block = 4;
+    e->item_order = 0;
     for (int l = 0; l < nlev; ++l) {
-        const LevelArgs &L = e->levels[l];
         int lane62 = 0;
-        const int nstrip = strips_of(e, L, &lane62);
-        std::vector<std::pair<double, int>> ranked;
-        std::vector<int> seen;
-        for (int nch = 1; nch <= std::min(L.ny, 256); ++nch) {
-            int chunk = (L.ny + nch - 1) / nch;
-            if (chunk < 4)
-                chunk = 4;
-            if (std::find(seen.begin(), seen.end(), chunk) != seen.end())
-                continue;
-            seen.push_back(chunk);
-            const long long items = (long long)L.R * nstrip * ((L.ny + chunk - 1) / chunk);
-            const long long rounds = (items + waves - 1) / waves;
-            ranked.push_back({(double)rounds * (chunk + 4), chunk});
-        }
-        std::sort(ranked.begin(), ranked.end());
-        for (int i = 0; i < (int)ranked.size() && i < max_cand; ++i)
-            cand[l].push_back(ranked[i].second);
-        const int dflt = model_chunk(e, L, nstrip);
-        if (std::find(cand[l].begin(), cand[l].end(), dflt) == cand[l].end())
-            cand[l].push_back(dflt);
+        dflt[l] = model_chunk(e, e->levels[l], strips_of(e, e->levels[l], &lane62));
     }
-    size_t ncand = 0;
-    for (auto &c : cand)
-        ncand = std::max(ncand, c.size());
-    std::vector<hipEvent_t> ev(nlev + 1);
-    for (auto &x : ev)
-        HIP_TRY(hipEventCreate(&x));
-    std::vector<std::vector<double>> ms(nlev, std::vector<double>(ncand, 0.0));
+    std::vector<std::vector<int>> tuples = chunk_candidates(e, 6);
+    if (std::find(tuples.begin(), tuples.end(), dflt) == tuples.end())
+        tuples.push_back(dflt);
+
+    hipEvent_t ev[2];
+    HIP_TRY(hipEventCreate(&ev[0]));
+    HIP_TRY(hipEventCreate(&ev[1]));
     const PhysArgs ph = phys_args(e->p);
     vlbm_status rc = VLBM_OK;
     bool all_done = false;
-    for (size_t ci = 0; ci < ncand && rc == VLBM_OK && !all_done; ++ci) {
-        for (int l = 0; l < nlev; ++l)
-            e->level_chunk[l] = cand[l][std::min(ci, cand[l].size() - 1)];
-        for (int s = 0; s < steps_per_candidate && rc == VLBM_OK; ++s) {
-            const int phase = phase_of(e);
-            for (int l = 0; l < nlev && rc == VLBM_OK; ++l) {
-                if (hipEventRecord(ev[l], e->stream) != hipSuccess)
-                    rc = fail(VLBM_ERR_HIP, "hipEventRecord failed");
-                else
-                    rc = launch_step(e, ph, l, l + 1, phase, t_final, e->stream);
-            }
-            if (rc != VLBM_OK)
-                break;
-            e->n_launch++;
-            if (hipEventRecord(ev[nlev], e->stream) != hipSuccess || hipEventSynchronize(ev[nlev]) != hipSuccess) {
-                rc = fail(VLBM_ERR_HIP, "event synchronisation failed");
-                break;
-            }
-            for (int l = 0; l < nlev; ++l) {
-                float t = 0.f;
-                (void)hipEventElapsedTime(&t, ev[l], ev[l + 1]);
-                ms[l][ci] += t;
-            }
+    // time the current configuration: average launch time, or < 0 if the
+    // ensemble finished (or failed) before it could be timed
+    auto time_config = [&]() -> double {
+        if (all_done || rc != VLBM_OK)
+            return -1.0;
+        if (hipEventRecord(ev[0], e->stream) != hipSuccess) {
+            rc = fail(VLBM_ERR_HIP, "hipEventRecord failed");
+            return -1.0;
         }
-        // stop early if the ensemble has finished (timings would be meaningless)
+        for (int s = 0; s < steps_per_candidate && rc == VLBM_OK; ++s) {
+            rc = launch_step(e, ph, 0, nlev, phase_of(e), t_final, e->stream);
+            if (rc == VLBM_OK)
+                e->n_launch++;
+        }
+        if (rc != VLBM_OK)
+            return -1.0;
+        if (hipEventRecord(ev[1], e->stream) != hipSuccess || hipEventSynchronize(ev[1]) != hipSuccess) {
+            rc = fail(VLBM_ERR_HIP, "event synchronisation failed");
+            return -1.0;
+        }
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, ev[0], ev[1]);
         std::vector<double> t, a;
         std::vector<long long> st;
         std::vector<int> status;
-        if (rc == VLBM_OK && read_ctl(e, t, st, a, status) == VLBM_OK) {
+        if ((rc = read_ctl(e, t, st, a, status)) != VLBM_OK)
+            return -1.0;
+        bool done = true;
+        for (double x : t)
+            done = done && x >= t_final;
+        if (done) { // the last launches may have had nothing left to do
             all_done = true;
-            for (double x : t)
-                if (x < t_final)
-                    all_done = false;
-            if (all_done && ci == 0)
-                ms.assign(nlev, std::vector<double>(ncand, 0.0));
+            return -1.0;
         }
-    }
-    for (auto &x : ev)
-        (void)hipEventDestroy(x);
+        return (double)ms / steps_per_candidate;
+    };
+    TuneChoice best;
+    best.chunks = dflt;
+    double best_ms = 1e300;
+    auto consider = [&](const std::vector<int> &chunks, int wpb, int order) {
+        e->level_chunk = chunks;
+        e->waves_per_block = wpb;
+        e->item_order = order;
+        const double ms = time_config();
+        if (ms > 0.0 && ms < best_ms) {
+            best_ms = ms;
+            best.chunks = chunks;
+            best.waves_per_block = wpb;
+            best.item_order = order;
+        }
+    };
+    for (const auto &t : tuples)
+        consider(t, 4, 0);
+    const std::vector<int> best_chunks = best.chunks;
+    consider(best_chunks, 2, 0);
+    consider(best_chunks, 1, 0);
+    consider(best_chunks, best.waves_per_block, 1);
+    (void)hipEventDestroy(ev[0]);
+    (void)hipEventDestroy(ev[1]);
+    e->level_chunk = best.chunks;
+    e->waves_per_block = best.waves_per_block;
+    e->item_order = best.item_order;
     if (rc != VLBM_OK)
         return rc;
-    std::lock_guard<std::mutex> lk(g_tune_mu);
-    for (int l = 0; l < nlev; ++l) {
-        int best = cand[l][0];
-        double best_ms = 1e300;
-        for (size_t ci = 0; ci < cand[l].size(); ++ci)
-            if (ms[l][ci] > 0.0 && ms[l][ci] < best_ms) {
-                best_ms = ms[l][ci];
-                best = cand[l][ci];
-            }
-        e->level_chunk[l] = best;
-        g_tune_cache[tune_key(e, e->levels[l])] = best;
-        if (chunks_out)
-            chunks_out[l] = best;
+    if (best_ms < 1e300) {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        g_tune_cache[tune_key(e)] = best;
     }
+    report();
     return VLBM_OK;
 }
 

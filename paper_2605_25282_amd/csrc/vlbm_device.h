@@ -512,6 +512,10 @@ struct MarchArgs {
     int chunk;       // rows per work item
     int nchunk;      // row chunks per realization
     int lane62_last; // 1: lane 62 of the last strip writes the copy column nx-1
+    int order;       // work-item order: 0 strip fastest (consecutive items are
+                     // neighbouring strips of one realization), 1 realization
+                     // fastest (consecutive items are one tile of consecutive
+                     // realizations)
 };
 
 // All mesh levels advanced by one launch: work items are concatenated level by
@@ -519,7 +523,8 @@ struct MarchArgs {
 static constexpr int MAX_LEVELS = 8;
 struct MultiLevel {
     int nlev;
-    int nblocks;                   // logical blocks (4 waves each) of the grid
+    int wpb;                       // wavefronts per block (1, 2 or 4)
+    int nblocks;                   // logical blocks (wpb waves each) of the grid
     int per_xcd;                   // logical blocks per XCD slot
     long long item_off[MAX_LEVELS + 1];
     LevelArgs L[MAX_LEVELS];

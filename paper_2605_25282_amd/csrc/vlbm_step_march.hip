@@ -30,9 +30,11 @@
 // rows) are produced by the wave that owns the copied interior node.
 //
 // Work items (realization, row chunk, strip) of every mesh level are ordered
-// strip-fastest and dealt round-robin to a grid sized to the resident
-// capacity of the chip; blocks are renumbered so that consecutive items land
-// on one XCD (shared L2 for the halo re-reads of neighbouring strips).
+// strip-fastest (or realization-fastest, a tuning choice) and dealt
+// round-robin to a grid of blocks of 1, 2 or 4 wavefronts sized to the
+// resident capacity of the chip; blocks are renumbered so that consecutive
+// items land on one XCD (shared L2 for the halo re-reads of neighbouring
+// strips).
 #include "vlbm_device.h"
 
 namespace vlbm {
@@ -68,9 +70,15 @@ template <int PREC>
 __device__ __forceinline__ void march_item(const PhysArgs &ph, const LevelArgs &L, const MarchArgs &ma,
                                            const Ctl &ctl, int phase, double t_final, long long item, int lane)
 {
-    const long long per_real = (long long)ma.nstrip * ma.nchunk;
-    const int m = (int)(item / per_real);
-    const int rem = (int)(item % per_real);
+    int m, rem;
+    if (ma.order == 0) { // strip fastest
+        const long long per_real = (long long)ma.nstrip * ma.nchunk;
+        m = (int)(item / per_real);
+        rem = (int)(item % per_real);
+    } else { // realization fastest
+        m = (int)(item % L.R);
+        rem = (int)(item / L.R);
+    }
     const int chunk = rem / ma.nstrip, strip = rem % ma.nstrip;
 
     // ---- time-step control (identical in every wave of the realization) ----
@@ -460,12 +468,12 @@ step_march_kernel(PhysArgs ph, MultiLevel ml, Ctl ctl, int phase, double t_final
         return;
     const int lane = threadIdx.x & 63;
     const long long n_items = ml.item_off[ml.nlev];
-    const long long grid_waves = (long long)ml.nblocks * 4;
+    const long long grid_waves = (long long)ml.nblocks * ml.wpb;
     // the wave index is uniform across the wave: keep it (and everything derived
     // from it: work item, realization, plane bases, time control) in scalar registers
     const int wid = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     int l = 0;
-    for (long long item = (long long)lb * 4 + wid; item < n_items; item += grid_waves) {
+    for (long long item = (long long)lb * ml.wpb + wid; item < n_items; item += grid_waves) {
         while (item >= ml.item_off[l + 1])
             ++l;
         march_item<PREC>(ph, ml.L[l], ml.ma[l], ctl, phase, t_final, item - ml.item_off[l], lane);

@@ -345,6 +345,8 @@ def test_autotune_is_result_neutral_and_cached():
     a = vlbm.Ensemble(vlbm.Params.jet(), [(w.nx, w.ny, w.dx, w.y_min)], coefs, R)
     chunks = a.autotune(1e30, steps_per_candidate=2)
     assert len(chunks) == 1 and 4 <= chunks[0] <= w.ny
+    tuned = a.get_tuning()
+    assert tuned[0] == chunks and tuned[1] in (1, 2, 4) and tuned[2] in (0, 1)
     n_tune = int(a.times(0)[1][0])
     a.step(1e30, 40 - n_tune)
     b = vlbm.Ensemble(vlbm.Params.jet(), [(w.nx, w.ny, w.dx, w.y_min)], coefs, R)
@@ -353,10 +355,44 @@ def test_autotune_is_result_neutral_and_cached():
     sa, sb = a.state(0).cpu().numpy(), b.state(0).cpu().numpy()
     assert np.array_equal(sa, sb)
     c = vlbm.Ensemble(vlbm.Params.jet(), [(w.nx, w.ny, w.dx, w.y_min)], coefs, R)
+    assert c.get_tuning() == tuned  # the cached choice
     c.step(1e30, 40)
     assert np.array_equal(c.state(0).cpu().numpy(), sa)
     for e in (a, b, c):
         e.close()
+
+
+def test_every_decomposition_is_bitwise_equal():
+    """Two levels in one launch under every decomposition the tuner can pick --
+    uneven chunk heights, 1, 2 or 4 wavefronts per block, strip-fastest or
+    realization-fastest items -- give the same states bit for bit, and
+    vlbm_get_tuning reports what vlbm_set_tuning set."""
+    R = 5
+    levels = _three_levels(64)[:2]
+    coefs = inputs.kl_coefficients(inputs.DEFAULT_SEED, 0, R)
+    ref = None
+    for chunks, wpb, order in (([0, 0], 4, 0), ([7, 13], 4, 0), ([7, 13], 2, 0), ([7, 13], 1, 0),
+                               ([5, 64], 4, 1), ([9, 4], 2, 1), ([32, 11], 1, 1)):
+        e = vlbm.Ensemble(vlbm.Params.jet(), levels, coefs, R)
+        e.set_tuning(chunks, wpb, order)
+        got_chunks, got_wpb, got_order = e.get_tuning()
+        assert (got_wpb, got_order) == (wpb, order)
+        assert all(g == (min(c, ny) if c else g) for g, c, (_, ny, _, _) in zip(got_chunks, chunks, levels))
+        e.step(1e30, 45)
+        st = [e.state(l).cpu().numpy() for l in range(2)]
+        clocks = [e.times(l)[:2] for l in range(2)]
+        e.close()
+        if ref is None:
+            ref = (st, clocks)
+            continue
+        for l in range(2):
+            assert np.array_equal(st[l], ref[0][l]), (chunks, wpb, order, l)
+            assert np.array_equal(clocks[l][0], ref[1][l][0]) and np.array_equal(clocks[l][1], ref[1][l][1])
+    e = vlbm.Ensemble(vlbm.Params.jet(), levels, coefs, R)
+    for bad in ((None, 3, 0), (None, 4, 2), ([2, 0], 4, 0)):
+        with pytest.raises(vlbm.VlbmError):
+            e.set_tuning(*bad)
+    e.close()
 
 
 def _three_levels(nx0):
