@@ -60,10 +60,11 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(precision: str, workload: str):
+def measured_traffic(precision: str, workload: str, node_updates_per_launch: float | None = None):
     """HBM bytes per launch of the step kernel from the committed rocprofv3
     counter summary of this workload, if it was taken on the current kernel
-    sources (null for a workload without one)."""
+    sources (null for a workload without one), scaled to this run's node
+    updates per launch when the record states its own (a different batch)."""
     path = os.path.join(ROOT, "profiles", f"traffic_step_{workload}_{precision}.json")
     if not os.path.exists(path):
         return None
@@ -71,7 +72,11 @@ def measured_traffic(precision: str, workload: str):
         d = json.load(f)
     if d.get("kernel_source_hash") != kernel_source_hash():
         return None
-    return d.get("bytes_per_launch")
+    per_launch = d.get("bytes_per_launch")
+    rec = d.get("node_updates_per_launch")
+    if per_launch is not None and rec and node_updates_per_launch:
+        per_launch = per_launch * node_updates_per_launch / rec
+    return per_launch
 
 
 def cpu_baseline(name, nx, ny, dx, y_min, steps=None, seconds_target: float = 15.0,
@@ -150,6 +155,10 @@ def main() -> int:
                          "configuration, e.g. for a profiler run of this same command)")
     ap.add_argument("--chunk-rows", type=int, default=0,
                     help="rows per wave of the step kernel (0: autotuned / default)")
+    ap.add_argument("--decomposition", default="",
+                    help="with --no-tune, c5: the step kernel's whole decomposition as "
+                         "CHUNKS:WAVES_PER_BLOCK:ITEM_ORDER:DEALING, CHUNKS comma-separated per level "
+                         "(coarse, fine), e.g. 79,79:4:0:1 (a profiler run of a tuned configuration)")
     ap.add_argument("--mixed-error", action="store_true",
                     help="instead of the default line: statistics of a mixed and of a one-ulp-"
                          "perturbed FP64 ensemble against an FP64 ensemble of the same seeds, at "
@@ -351,7 +360,10 @@ def run_headline(args, torch, vlbm, inputs) -> int:
         prec = variants[0]
         ens = vlbm.Ensemble(vlbm.Params.jet(precision=prec), levels,
                             vlbm.vlbm_kl_coefficients(inputs.DEFAULT_SEED, 0, B), B)
-        if args.chunk_rows:
+        if args.decomposition:
+            ch, wpb, order, deal = args.decomposition.split(":")
+            ens.set_tuning([int(c) for c in ch.split(",")], int(wpb), int(order), int(deal))
+        elif args.chunk_rows:
             ens.tune("march", args.chunk_rows)
         ens.step(t_final, args.profile_launches, want_done=True)
         ens.close()
@@ -385,11 +397,15 @@ def run_headline(args, torch, vlbm, inputs) -> int:
         ens = vlbm.Ensemble(params, levels, coefs, B)
         if not args.no_tune:
             ens.autotune(t_final, 8)  # live steps, counted toward t_final
+        elif args.decomposition:
+            ch, wpb, order, deal = args.decomposition.split(":")
+            ens.set_tuning([int(c) for c in ch.split(",")], int(wpb), int(order), int(deal))
         elif args.chunk_rows:
             ens.tune("march", args.chunk_rows)
-        chunks, wpb, order = ens.get_tuning()
+        chunks, wpb, order, deal = ens.get_tuning()
         tuned = {"rows_per_wave": chunks, "waves_per_block": wpb,
                  "item_order": "strip fastest" if order == 0 else "realization fastest",
+                 "dealing": "static round-robin" if deal == 0 else "per-XCD work queues",
                  "autotuned": not args.no_tune}
         progress(f"{prec}: step kernel decomposition {tuned}")
         acc_step = {"step_ms": 0.0, "stats_s": 0.0}
@@ -491,7 +507,7 @@ def run_headline(args, torch, vlbm, inputs) -> int:
                    "once_per_job_sort_and_w1_of_the_full_stores_ms": round(final_ms, 1)},
         "roofline": {"bound": "hbm", "achieved": round(r0["achieved"], 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(r0["achieved"] / HBM_PEAK_GBS, 4),
-                     "traffic": measured_traffic(head, "c5"),
+                     "traffic": measured_traffic(head, "c5", B * lup_per_launch_per_real),
                      "kernel": "vlbm step kernel (both levels per launch)", "bytes_per_node_update": bpl,
                      "avg_launch_ms": round(r0["avg_launch_ms"], 4),
                      "device_copy_GBs": round(copy_gbs, 1),
@@ -506,7 +522,7 @@ def run_headline(args, torch, vlbm, inputs) -> int:
             "speedup_vs_fp64": round(rm["value"] / r0["value"], 4),
             "roofline": {"bound": "hbm", "achieved": round(rm["achieved"], 1), "peak": HBM_PEAK_GBS,
                          "unit": "GB/s", "frac": round(rm["achieved"] / HBM_PEAK_GBS, 4),
-                         "traffic": measured_traffic("mixed", "c5"),
+                         "traffic": measured_traffic("mixed", "c5", B * lup_per_launch_per_real),
                          "bytes_per_node_update": BYTES_PER_LUP["mixed"],
                          "avg_launch_ms": round(rm["avg_launch_ms"], 4),
                          "frac_of_device_copy": round(rm["achieved"] / copy_gbs, 4)},
@@ -516,12 +532,15 @@ def run_headline(args, torch, vlbm, inputs) -> int:
         if not args.no_mixed_error:
             out["mixed"]["error_vs_fp64"] = mixed_error_study(torch, vlbm, inputs, inputs.WORKLOADS["jet640"],
                                                               (0.01, 0.1, 1.0), 240)
-    for key in ("roofline",):
-        tr = out[key].get("traffic")
+    rooflines = [(out["roofline"], bpl)]
+    if "mixed" in out:
+        rooflines.append((out["mixed"]["roofline"], BYTES_PER_LUP["mixed"]))
+    for roof, alg in rooflines:
+        tr = roof.get("traffic")
         if tr:
             per_lup = tr / (B * lup_per_launch_per_real)
-            out[key]["hbm_bytes_per_node_update"] = round(per_lup, 1)
-            out[key]["hbm_GBs_implied"] = round(out[key]["achieved"] * per_lup / bpl, 1)
+            roof["hbm_bytes_per_node_update"] = round(per_lup, 1)
+            roof["hbm_GBs_implied"] = round(roof["achieved"] * per_lup / alg, 1)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(fine.name, fine.nx, fine.ny, fine.dx, fine.y_min, steps=3)
     print(json.dumps(out), flush=True)

@@ -365,37 +365,43 @@ vlbm_status vlbm_rate_fit(const double *errors, const double *dx, int32_t n, dou
  * Select the step kernel and its work decomposition for this ensemble:
  * chunk_rows is the number of rows one wavefront marches over, for every
  * level (0 = chosen from the level sizes and ensemble size; otherwise
- * 4 <= chunk_rows <= 65536); blocks return to 4 wavefronts and the
- * strip-fastest item order.  Results do not depend on the choice (every
- * kernel and decomposition is bit-identical); only the speed does.
+ * 4 <= chunk_rows <= 65536); blocks return to 4 wavefronts, the
+ * strip-fastest item order and the work-queue dealing (the defaults).  Results
+ * do not depend on the choice (every kernel and decomposition is
+ * bit-identical); only the speed does.
  */
 vlbm_status vlbm_tune(vlbm_ensemble *e, int32_t kernel, int32_t chunk_rows);
 
 /*
  * The marching kernel's decomposition, all of it: chunks (HOST [n_levels]:
  * rows per work item of each level, 0 = the default of that level; NULL = all
- * defaults), waves_per_block (1, 2 or 4 wavefronts per block) and item_order
+ * defaults), waves_per_block (1, 2 or 4 wavefronts per block), item_order
  * (0: consecutive work items are neighbouring column strips of one
  * realization; 1: they are the same tile of consecutive realizations, so a
- * block of w wavefronts holds w realizations).  Bit-identical results for
- * every choice.  VLBM_ERR_ARG on values outside these sets.
+ * block of w wavefronts holds w realizations) and dealing (0: item i goes to
+ * wavefront i mod W, fixed; 1, the default: the items are split into one
+ * contiguous range per XCD and every wavefront takes the next item of its
+ * XCD's range, then of the other XCDs' ranges, from counters in the control
+ * block, so faster wavefronts take more).
+ * Bit-identical results for every choice.  VLBM_ERR_ARG on values outside
+ * these sets.
  */
 vlbm_status vlbm_set_tuning(vlbm_ensemble *e, const int32_t *chunks, int32_t waves_per_block,
-                            int32_t item_order);
+                            int32_t item_order, int32_t dealing);
 /* The decomposition in use (chunks: HOST [n_levels] or NULL; others nullable). */
 vlbm_status vlbm_get_tuning(const vlbm_ensemble *e, int32_t *chunks, int32_t *waves_per_block,
-                            int32_t *item_order);
+                            int32_t *item_order, int32_t *dealing);
 
 /*
  * Autotune the marching kernel's decomposition for the whole launch (all
  * levels together, as vlbm_step runs them) on live steps.  Candidate chunk
  * tuples come from common target heights (each level splits its rows evenly
- * near the target) and are ranked by a model of the static round-robin
- * dealing (the launch lasts as long as the wavefront with the most rows,
- * 4-row prologue per item included); the best few, then 2 and 1 wavefronts per
- * block and the realization-fastest item order around the fastest tuple, are
- * each timed over steps_per_candidate real steps (HIP events on the
- * ensemble's stream) and the fastest configuration is kept.  The steps taken
+ * near the target) and are ranked by a work model of each dealing (rows per
+ * item plus the 4-row prologue; work queues: the average load per wavefront
+ * plus one item; static round-robin: the most loaded wavefront); the best few
+ * of each, then 2 and 1 wavefronts per block and the realization-fastest item
+ * order around the fastest, are each timed over steps_per_candidate real steps
+ * (HIP events on the ensemble's stream) and the fastest configuration is kept.  The steps taken
  * are ordinary steps toward t_final (every configuration is bit-identical), so
  * tuning wastes no work.  The choice is cached per (precision, bc, limiter,
  * n_real, every level's nx and ny) for the lifetime of the process and applied

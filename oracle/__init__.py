@@ -26,7 +26,9 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "vlbm_oracle.c")
-_LIB = os.path.join(_HERE, "libvlbm_oracle.so")
+# ORACLE_LIB names another build of vlbm_oracle.c to load (the sanitizer test
+# runs the oracle from an AddressSanitizer / UBSan build this way)
+_LIB = os.environ.get("ORACLE_LIB") or os.path.join(_HERE, "libvlbm_oracle.so")
 
 BC = {"jet": 0, "periodic": 1, "neumann": 2}
 THETA = {"limiter": 0, "zero": 1, "one": 2, "given": 3}

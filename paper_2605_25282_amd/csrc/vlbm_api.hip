@@ -81,6 +81,15 @@ vlbm_status fail(vlbm_status code, const char *fmt, ...)
 // Bytes of one state buffer: R x ny row blocks of 20 plane rows, each plane row
 // 64 element slots per column strip (FP64: 160 B per slot; mixed: 8 FP64 and
 // 12 FP32 planes, 112 B per slot).
+// Bytes of the per-ensemble control block: the three-launch ring of time, kinetic
+// speed, step count and wave-speed maximum, the status words, and the nine
+// counters of the dynamic work dealing.
+size_t ctl_block_bytes(int nr)
+{
+    return (size_t)3 * nr * (sizeof(double) * 2 + sizeof(long long) + sizeof(unsigned long long)) +
+           (size_t)nr * sizeof(int) + 9 * sizeof(unsigned);
+}
+
 size_t state_bytes(int prec, int bc, int nx, int ny, int R)
 {
     const size_t slots = (size_t)SLOTS * (size_t)strip_count(nx, bc == VLBM_BC_PERIODIC);
@@ -162,6 +171,7 @@ struct vlbm_ensemble {
     int march_blocks_per_cu[3] = {4, 2, 1}; // resident blocks per CU for 1, 2, 4 waves per block
     int waves_per_block = 4; // wavefronts per block of the marching kernel (1, 2 or 4)
     int item_order = 0;      // 0 strip fastest, 1 realization fastest
+    int dealing = 1;         // 0 static round-robin, 1 per-XCD work queues (default)
     std::vector<int> level_chunk; // per-level chunk override (0 = from chunk_rows / model)
     // hipGraph of GRAPH_STEPS consecutive steps (ring phases 0,1,2,...), captured on
     // an internal stream and replayed on the ensemble's stream
@@ -182,6 +192,7 @@ struct TuneChoice {
     std::vector<int> chunks;
     int waves_per_block = 4;
     int item_order = 0;
+    int dealing = 1;
 };
 std::map<TuneKey, TuneChoice> g_tune_cache;
 std::mutex g_tune_mu;
@@ -219,16 +230,18 @@ long long resident_waves(const vlbm_ensemble *e)
     return (long long)e->n_cu * e->march_blocks_per_cu[wpb_index(wpb)] * wpb;
 }
 
-// Default chunk height: about twelve work items per resident wave, rows >= 16.
+// Default chunk height: the even split of the rows nearest 64 (short items keep
+// neighbouring strips in step and let the work queues balance finely), split
+// further while there are fewer than eight items per resident wave; rows >= 16.
 int model_chunk(const vlbm_ensemble *e, const LevelArgs &L, int nstrip)
 {
-    const long long target = 12LL * resident_waves(e);
+    const long long target = 8LL * resident_waves(e);
     const long long per_chunk = (long long)L.R * nstrip;
-    long long nch = (target + per_chunk - 1) / per_chunk;
-    if (nch < 1)
-        nch = 1;
-    int chunk = (int)((L.ny + nch - 1) / nch);
-    return chunk < 16 ? 16 : chunk;
+    int nch = std::max(1, (L.ny + 32) / 64);
+    while ((long long)nch * per_chunk < target && (L.ny + nch) / (nch + 1) >= 16)
+        ++nch;
+    int chunk = (L.ny + nch - 1) / nch;
+    return chunk < 16 ? std::min(16, L.ny) : chunk;
 }
 
 MarchArgs march_args(const vlbm_ensemble *e, int level)
@@ -263,6 +276,7 @@ MultiLevel multi_level(const vlbm_ensemble *e, int l0, int l1, unsigned *grid)
     }
     const int wpb = e->waves_per_block;
     ml.wpb = wpb;
+    ml.dynamic = e->dealing;
     long long blocks = (ml.item_off[ml.nlev] + wpb - 1) / wpb;
     const long long resident = resident_waves(e) / wpb;
     if (blocks > resident)
@@ -409,8 +423,7 @@ vlbm_status vlbm_init_ensemble(const vlbm_params *p, const vlbm_level *levels, i
                     l * n_real, levels[l].dx, levels[l].y_min, {levels[l].state[0], levels[l].state[1]}};
         e->levels.push_back(L);
     }
-    const size_t ctl_bytes = (size_t)3 * nr * (sizeof(double) * 2 + sizeof(long long) + sizeof(unsigned long long)) +
-                             (size_t)nr * sizeof(int);
+    const size_t ctl_bytes = ctl_block_bytes(nr);
     hipError_t he = hipMalloc(&e->ctl_mem, ctl_bytes);
     if (he != hipSuccess) {
         delete e;
@@ -426,6 +439,8 @@ vlbm_status vlbm_init_ensemble(const vlbm_params *p, const vlbm_level *levels, i
     e->ctl.amax = (unsigned long long *)c;
     c += 3 * nr * sizeof(unsigned long long);
     e->ctl.status = (int *)c;
+    c += nr * sizeof(int);
+    e->ctl.work = (unsigned *)c;
     e->ctl.nr = nr;
     const size_t ncoef = (size_t)n_real * 2 * p->kl_modes;
     if (ncoef > 0) {
@@ -481,6 +496,7 @@ vlbm_status vlbm_init_ensemble(const vlbm_params *p, const vlbm_level *levels, i
             e->level_chunk = it->second.chunks;
             e->waves_per_block = it->second.waves_per_block;
             e->item_order = it->second.item_order;
+            e->dealing = it->second.dealing;
         }
     }
     // The host coefficient array may be released once this call returns.
@@ -520,7 +536,7 @@ vlbm_status rebase_ring(vlbm_ensemble *e, int level, const double *t_lvl, const 
         status[L.ctl_off + m] = 0;
         amax[L.ctl_off + m] = 0ull;
     }
-    HIP_TRY(hipMemsetAsync(e->ctl_mem, 0, (size_t)3 * nr * (sizeof(double) * 2 + sizeof(long long) + sizeof(unsigned long long)) + nr * sizeof(int), e->stream));
+    HIP_TRY(hipMemsetAsync(e->ctl_mem, 0, ctl_block_bytes(nr), e->stream));
     HIP_TRY(hipMemcpyAsync(e->ctl.t, t.data(), nr * sizeof(double), hipMemcpyHostToDevice, e->stream));
     HIP_TRY(hipMemcpyAsync(e->ctl.steps, steps.data(), nr * sizeof(long long), hipMemcpyHostToDevice, e->stream));
     HIP_TRY(hipMemcpyAsync(e->ctl.a_last, a.data(), nr * sizeof(double), hipMemcpyHostToDevice, e->stream));
@@ -1032,11 +1048,13 @@ vlbm_status vlbm_tune(vlbm_ensemble *e, int32_t kernel, int32_t chunk_rows)
     std::fill(e->level_chunk.begin(), e->level_chunk.end(), 0);
     e->waves_per_block = 4;
     e->item_order = 0;
+    e->dealing = 1;
     drop_graph(e);
     return VLBM_OK;
 }
 
-vlbm_status vlbm_set_tuning(vlbm_ensemble *e, const int32_t *chunks, int32_t waves_per_block, int32_t item_order)
+vlbm_status vlbm_set_tuning(vlbm_ensemble *e, const int32_t *chunks, int32_t waves_per_block, int32_t item_order,
+                            int32_t dealing)
 {
     if (!e)
         return fail(VLBM_ERR_ARG, "ensemble is NULL");
@@ -1044,6 +1062,8 @@ vlbm_status vlbm_set_tuning(vlbm_ensemble *e, const int32_t *chunks, int32_t wav
         return fail(VLBM_ERR_ARG, "waves_per_block must be 1, 2 or 4 (got %d)", waves_per_block);
     if (item_order != 0 && item_order != 1)
         return fail(VLBM_ERR_ARG, "item_order must be 0 or 1 (got %d)", item_order);
+    if (dealing != 0 && dealing != 1)
+        return fail(VLBM_ERR_ARG, "dealing must be 0 or 1 (got %d)", dealing);
     if (chunks)
         for (size_t l = 0; l < e->levels.size(); ++l)
             if (chunks[l] != 0 && (chunks[l] < 4 || chunks[l] > 65536))
@@ -1052,11 +1072,13 @@ vlbm_status vlbm_set_tuning(vlbm_ensemble *e, const int32_t *chunks, int32_t wav
         e->level_chunk[l] = chunks ? chunks[l] : 0;
     e->waves_per_block = waves_per_block;
     e->item_order = item_order;
+    e->dealing = dealing;
     drop_graph(e);
     return VLBM_OK;
 }
 
-vlbm_status vlbm_get_tuning(const vlbm_ensemble *e, int32_t *chunks, int32_t *waves_per_block, int32_t *item_order)
+vlbm_status vlbm_get_tuning(const vlbm_ensemble *e, int32_t *chunks, int32_t *waves_per_block, int32_t *item_order,
+                            int32_t *dealing)
 {
     if (!e)
         return fail(VLBM_ERR_ARG, "ensemble is NULL");
@@ -1067,14 +1089,18 @@ vlbm_status vlbm_get_tuning(const vlbm_ensemble *e, int32_t *chunks, int32_t *wa
         *waves_per_block = e->waves_per_block;
     if (item_order)
         *item_order = e->item_order;
+    if (dealing)
+        *dealing = e->dealing;
     return VLBM_OK;
 }
 
 namespace {
-// Work model of one launch under the static round-robin dealing: every work
-// item costs its rows plus the 4-row prologue of the march, item i goes to
-// wave i mod W, and the launch lasts as long as the most loaded wave.
-double dealing_model(const vlbm_ensemble *e, const std::vector<int> &chunks)
+// Work models of one launch: every work item costs its rows plus the 4-row
+// prologue of the march.  Static round-robin dealing: item i goes to wave
+// i mod W and the launch lasts as long as the most loaded wave.  Work queues:
+// the work spreads evenly and the launch lasts the average load plus at most one
+// item (the last ones handed out).
+double dealing_model(const vlbm_ensemble *e, const std::vector<int> &chunks, int dealing)
 {
     const long long W = resident_waves(e);
     std::vector<double> load((size_t)W, 0.0);
@@ -1094,33 +1120,49 @@ double dealing_model(const vlbm_ensemble *e, const std::vector<int> &chunks)
             load[(size_t)(i % W)] += rows + 4;
         }
     }
-    return *std::max_element(load.begin(), load.end());
+    if (dealing == 0)
+        return *std::max_element(load.begin(), load.end());
+    double total = 0.0;
+    for (double x : load)
+        total += x;
+    int longest = 0;
+    for (size_t l = 0; l < e->levels.size(); ++l)
+        longest = std::max(longest, std::min(chunks[l], e->levels[l].ny));
+    return total / (double)W + longest + 4;
 }
 
 // Candidate chunk tuples: for every common target height h (the distinct heights
 // ny_l / n of all levels), each level takes the height of its even split closest
 // above h; tuples are ranked by the dealing model and the best `keep` returned.
-std::vector<std::vector<int>> chunk_candidates(const vlbm_ensemble *e, size_t keep)
+std::vector<std::vector<int>> chunk_candidates(const vlbm_ensemble *e, size_t keep, int dealing)
 {
     std::vector<int> targets;
-    for (const LevelArgs &L : e->levels)
-        for (int n = 1; n <= std::min(L.ny, 256); ++n) {
-            const int h = std::max(4, (L.ny + n - 1) / n);
-            if (std::find(targets.begin(), targets.end(), h) == targets.end())
-                targets.push_back(h);
-        }
+    if (dealing == 1) {
+        // work queues: the model cannot see how short items keep neighbouring
+        // strips in step, so a ladder of common heights is timed instead
+        for (int h : {32, 48, 64, 96, 128, 192, 256, 384})
+            targets.push_back(h);
+        keep = std::max(keep, targets.size());
+    } else {
+        for (const LevelArgs &L : e->levels)
+            for (int n = 1; n <= std::min(L.ny, 256); ++n) {
+                const int h = std::max(4, (L.ny + n - 1) / n);
+                if (std::find(targets.begin(), targets.end(), h) == targets.end())
+                    targets.push_back(h);
+            }
+    }
     std::vector<std::pair<double, std::vector<int>>> ranked;
     for (int h : targets) {
         std::vector<int> t;
         for (const LevelArgs &L : e->levels) {
             const int n = std::max(1, L.ny / h);
-            t.push_back(std::max(4, (L.ny + n - 1) / n));
+            t.push_back(std::min(L.ny, std::max(4, (L.ny + n - 1) / n)));
         }
         bool seen = false;
         for (auto &r : ranked)
             seen = seen || r.second == t;
         if (!seen)
-            ranked.push_back({dealing_model(e, t), t});
+            ranked.push_back({dealing_model(e, t, dealing), t});
     }
     std::stable_sort(ranked.begin(), ranked.end(),
                      [](const std::pair<double, std::vector<int>> &a, const std::pair<double, std::vector<int>> &b) {
@@ -1152,21 +1194,23 @@ vlbm_status vlbm_autotune(vlbm_ensemble *e, double t_final, int32_t steps_per_ca
         return VLBM_OK;
     }
     drop_graph(e);
-    // A configuration is (chunk height per level, waves per block, item order),
-    // timed on steps_per_candidate live steps of the whole launch (all levels, as
-    // vlbm_step runs them).  Search: the chunk tuples first (4 waves per block,
-    // strip-fastest order), ranked by the dealing model, then the block size and
-    // the item order around the fastest tuple.
+    // A configuration is (chunk height per level, waves per block, item order,
+    // dealing), timed on steps_per_candidate live steps of the whole launch (all
+    // levels, as vlbm_step runs them).  Search: chunk tuples under the work
+    // queues and under the static dealing, each ranked by its model, then the
+    // block size and the item order around the fastest.
     std::vector<int> dflt(nlev);
     e->waves_per_block = 4;
     e->item_order = 0;
+    e->dealing = 1;
     for (int l = 0; l < nlev; ++l) {
         int lane62 = 0;
         dflt[l] = model_chunk(e, e->levels[l], strips_of(e, e->levels[l], &lane62));
     }
-    std::vector<std::vector<int>> tuples = chunk_candidates(e, 6);
-    if (std::find(tuples.begin(), tuples.end(), dflt) == tuples.end())
-        tuples.push_back(dflt);
+    std::vector<std::vector<int>> dyn_tuples = chunk_candidates(e, 5, 1);
+    if (std::find(dyn_tuples.begin(), dyn_tuples.end(), dflt) == dyn_tuples.end())
+        dyn_tuples.push_back(dflt);
+    const std::vector<std::vector<int>> static_tuples = chunk_candidates(e, 2, 0);
 
     hipEvent_t ev[2];
     HIP_TRY(hipEventCreate(&ev[0]));
@@ -1212,30 +1256,37 @@ vlbm_status vlbm_autotune(vlbm_ensemble *e, double t_final, int32_t steps_per_ca
     };
     TuneChoice best;
     best.chunks = dflt;
+    best.dealing = 1;
     double best_ms = 1e300;
-    auto consider = [&](const std::vector<int> &chunks, int wpb, int order) {
+    auto consider = [&](const std::vector<int> &chunks, int wpb, int order, int dealing) {
         e->level_chunk = chunks;
         e->waves_per_block = wpb;
         e->item_order = order;
+        e->dealing = dealing;
         const double ms = time_config();
         if (ms > 0.0 && ms < best_ms) {
             best_ms = ms;
             best.chunks = chunks;
             best.waves_per_block = wpb;
             best.item_order = order;
+            best.dealing = dealing;
         }
     };
-    for (const auto &t : tuples)
-        consider(t, 4, 0);
+    for (const auto &t : dyn_tuples)
+        consider(t, 4, 0, 1);
+    for (const auto &t : static_tuples)
+        consider(t, 4, 0, 0);
     const std::vector<int> best_chunks = best.chunks;
-    consider(best_chunks, 2, 0);
-    consider(best_chunks, 1, 0);
-    consider(best_chunks, best.waves_per_block, 1);
+    const int best_dealing = best.dealing;
+    consider(best_chunks, 2, 0, best_dealing);
+    consider(best_chunks, 1, 0, best_dealing);
+    consider(best_chunks, best.waves_per_block, 1, best_dealing);
     (void)hipEventDestroy(ev[0]);
     (void)hipEventDestroy(ev[1]);
     e->level_chunk = best.chunks;
     e->waves_per_block = best.waves_per_block;
     e->item_order = best.item_order;
+    e->dealing = best.dealing;
     if (rc != VLBM_OK)
         return rc;
     if (best_ms < 1e300) {

@@ -255,6 +255,8 @@ struct Ctl {
     double *a_last;         // [3][NR] kinetic speed of the last step
     unsigned long long *amax; // [3][NR] max wave speed of the state (bits of a double >= 0)
     int *status;            // [NR] latched failure bits (1 nonpositive, 2 nonfinite)
+    unsigned *work;         // [9] dynamic dealing: next item of each XCD's range, then
+                            // the count of wavefronts that have left (reset to 0 by the last)
     int nr;                 // NR = number of (level, realization) pairs
 };
 
@@ -524,6 +526,7 @@ static constexpr int MAX_LEVELS = 8;
 struct MultiLevel {
     int nlev;
     int wpb;                       // wavefronts per block (1, 2 or 4)
+    int dynamic;                   // 0: static round-robin dealing; 1: per-XCD work queues
     int nblocks;                   // logical blocks (wpb waves each) of the grid
     int per_xcd;                   // logical blocks per XCD slot
     long long item_off[MAX_LEVELS + 1];

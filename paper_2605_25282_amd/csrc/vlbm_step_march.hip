@@ -464,19 +464,57 @@ step_march_kernel(PhysArgs ph, MultiLevel ml, Ctl ctl, int phase, double t_final
 {
     const int b = blockIdx.x;
     const int lb = (b & 7) * ml.per_xcd + (b >> 3);
-    if (lb >= ml.nblocks)
-        return;
     const int lane = threadIdx.x & 63;
     const long long n_items = ml.item_off[ml.nlev];
     const long long grid_waves = (long long)ml.nblocks * ml.wpb;
     // the wave index is uniform across the wave: keep it (and everything derived
     // from it: work item, realization, plane bases, time control) in scalar registers
     const int wid = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    // Static dealing: item i goes to wavefront i mod W.  Dynamic dealing: the
+    // items are split into 8 contiguous ranges, one per XCD (blocks are
+    // dispatched round-robin over the XCDs, so block b runs on XCD b mod 8 and
+    // neighbouring strips stay on one L2); every wavefront takes the next item of
+    // its XCD's range from a counter and, once that range is exhausted, of the
+    // following XCDs' ranges in turn, so the last items go to whichever
+    // wavefronts are free.  Each wavefront then counts itself out and the last
+    // one resets the counters for the next launch (no wavefront of this launch
+    // pulls any more by then, and the next launch starts after this one ended).
+    const bool dyn = ml.dynamic != 0;
+    if (!dyn && lb >= ml.nblocks)
+        return;
+    const int x0 = b & 7;
+    int r = 0; // ranges visited: XCD (x0 + r) mod 8
+    auto range_lo = [&](int k) -> long long { return n_items * ((x0 + k) & 7) / 8; };
+    auto range_hi = [&](int k) -> long long { return n_items * (((x0 + k) & 7) + 1) / 8; };
+    // next item of the current range, moving on through the ranges; n_items when all are done
+    auto pull = [&]() -> long long {
+        for (; r < 8; ++r) {
+            unsigned k = 0;
+            if (lane == 0)
+                k = atomicAdd(ctl.work + ((x0 + r) & 7), 1u);
+            const long long it = range_lo(r) + (long long)(unsigned)__builtin_amdgcn_readfirstlane((int)k);
+            if (it < range_hi(r))
+                return it;
+        }
+        return n_items;
+    };
+    long long item = dyn ? pull() : (long long)lb * ml.wpb + wid;
     int l = 0;
-    for (long long item = (long long)lb * ml.wpb + wid; item < n_items; item += grid_waves) {
+    while (item < n_items) {
+        if (dyn)
+            l = 0;
         while (item >= ml.item_off[l + 1])
             ++l;
         march_item<PREC>(ph, ml.L[l], ml.ma[l], ctl, phase, t_final, item - ml.item_off[l], lane);
+        item = dyn ? pull() : item + grid_waves;
+    }
+    if (dyn && lane == 0) {
+        const unsigned waves = gridDim.x * (blockDim.x >> 6);
+        if (atomicAdd(ctl.work + 8, 1u) == waves - 1) {
+#pragma unroll
+            for (int k = 0; k < 9; ++k)
+                atomicExch(ctl.work + k, 0u);
+        }
     }
 }
 

@@ -105,8 +105,9 @@ def lib():
             "vlbm_rate_fit": ([_DP, _DP, i32, _DP, _DP], i32),
             "vlbm_w12": ([_VP, _VP, i32, i32, i32, i32, _VP, _VP, _VP], i32),
             "vlbm_tune": ([_VP, i32, i32], i32),
-            "vlbm_set_tuning": ([_VP, ctypes.POINTER(i32), i32, i32], i32),
-            "vlbm_get_tuning": ([_VP, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32)], i32),
+            "vlbm_set_tuning": ([_VP, ctypes.POINTER(i32), i32, i32, i32], i32),
+            "vlbm_get_tuning": ([_VP, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32),
+                                 ctypes.POINTER(i32)], i32),
             "vlbm_autotune": ([_VP, dbl, i32, ctypes.POINTER(i32)], i32),
             "vlbm_destroy": ([_VP], i32),
         }
@@ -308,18 +309,18 @@ def vlbm_tune(h, kernel: str | int = "march", chunk_rows: int = 0) -> None:
     _check(lib().vlbm_tune(h, k, chunk_rows))
 
 
-def vlbm_set_tuning(h, chunks, waves_per_block: int = 4, item_order: int = 0) -> None:
+def vlbm_set_tuning(h, chunks, waves_per_block: int = 4, item_order: int = 0, dealing: int = 0) -> None:
     """chunks: rows per work item of every level (0 = default), or None for all defaults."""
     c = None if chunks is None else (ctypes.c_int32 * len(chunks))(*[int(x) for x in chunks])
-    _check(lib().vlbm_set_tuning(h, c, waves_per_block, item_order))
+    _check(lib().vlbm_set_tuning(h, c, waves_per_block, item_order, dealing))
 
 
-def vlbm_get_tuning(h, n_levels: int) -> tuple[list[int], int, int]:
-    """(chunk height of every level, waves per block, item order) in use."""
+def vlbm_get_tuning(h, n_levels: int) -> tuple[list[int], int, int, int]:
+    """(chunk height of every level, waves per block, item order, dealing) in use."""
     c = (ctypes.c_int32 * n_levels)()
-    w, o = ctypes.c_int32(0), ctypes.c_int32(0)
-    _check(lib().vlbm_get_tuning(h, c, ctypes.byref(w), ctypes.byref(o)))
-    return list(c), w.value, o.value
+    w, o, d = ctypes.c_int32(0), ctypes.c_int32(0), ctypes.c_int32(0)
+    _check(lib().vlbm_get_tuning(h, c, ctypes.byref(w), ctypes.byref(o), ctypes.byref(d)))
+    return list(c), w.value, o.value, d.value
 
 
 def vlbm_autotune(h, t_final: float, steps_per_candidate: int, n_levels: int) -> list[int]:
@@ -370,10 +371,10 @@ class Ensemble:
     def autotune(self, t_final: float, steps_per_candidate: int = 4) -> list[int]:
         return vlbm_autotune(self.h, t_final, steps_per_candidate, len(self.shapes))
 
-    def set_tuning(self, chunks=None, waves_per_block: int = 4, item_order: int = 0) -> None:
-        vlbm_set_tuning(self.h, chunks, waves_per_block, item_order)
+    def set_tuning(self, chunks=None, waves_per_block: int = 4, item_order: int = 0, dealing: int = 0) -> None:
+        vlbm_set_tuning(self.h, chunks, waves_per_block, item_order, dealing)
 
-    def get_tuning(self) -> tuple[list[int], int, int]:
+    def get_tuning(self) -> tuple[list[int], int, int, int]:
         return vlbm_get_tuning(self.h, len(self.shapes))
 
     def step(self, t_final: float, n_steps: int, want_done: bool = True):

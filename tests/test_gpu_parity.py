@@ -346,7 +346,7 @@ def test_autotune_is_result_neutral_and_cached():
     chunks = a.autotune(1e30, steps_per_candidate=2)
     assert len(chunks) == 1 and 4 <= chunks[0] <= w.ny
     tuned = a.get_tuning()
-    assert tuned[0] == chunks and tuned[1] in (1, 2, 4) and tuned[2] in (0, 1)
+    assert tuned[0] == chunks and tuned[1] in (1, 2, 4) and tuned[2] in (0, 1) and tuned[3] in (0, 1)
     n_tune = int(a.times(0)[1][0])
     a.step(1e30, 40 - n_tune)
     b = vlbm.Ensemble(vlbm.Params.jet(), [(w.nx, w.ny, w.dx, w.y_min)], coefs, R)
@@ -371,12 +371,14 @@ def test_every_decomposition_is_bitwise_equal():
     levels = _three_levels(64)[:2]
     coefs = inputs.kl_coefficients(inputs.DEFAULT_SEED, 0, R)
     ref = None
-    for chunks, wpb, order in (([0, 0], 4, 0), ([7, 13], 4, 0), ([7, 13], 2, 0), ([7, 13], 1, 0),
-                               ([5, 64], 4, 1), ([9, 4], 2, 1), ([32, 11], 1, 1)):
+    for chunks, wpb, order, deal in (([0, 0], 4, 0, 0), ([7, 13], 4, 0, 0), ([7, 13], 2, 0, 0),
+                                     ([7, 13], 1, 0, 0), ([5, 64], 4, 1, 0), ([9, 4], 2, 1, 0),
+                                     ([32, 11], 1, 1, 0), ([0, 0], 4, 0, 1), ([7, 13], 2, 1, 1),
+                                     ([5, 4], 1, 0, 1), ([64, 64], 4, 1, 1)):
         e = vlbm.Ensemble(vlbm.Params.jet(), levels, coefs, R)
-        e.set_tuning(chunks, wpb, order)
-        got_chunks, got_wpb, got_order = e.get_tuning()
-        assert (got_wpb, got_order) == (wpb, order)
+        e.set_tuning(chunks, wpb, order, deal)
+        got_chunks, got_wpb, got_order, got_deal = e.get_tuning()
+        assert (got_wpb, got_order, got_deal) == (wpb, order, deal)
         assert all(g == (min(c, ny) if c else g) for g, c, (_, ny, _, _) in zip(got_chunks, chunks, levels))
         e.step(1e30, 45)
         st = [e.state(l).cpu().numpy() for l in range(2)]
@@ -386,10 +388,10 @@ def test_every_decomposition_is_bitwise_equal():
             ref = (st, clocks)
             continue
         for l in range(2):
-            assert np.array_equal(st[l], ref[0][l]), (chunks, wpb, order, l)
+            assert np.array_equal(st[l], ref[0][l]), (chunks, wpb, order, deal, l)
             assert np.array_equal(clocks[l][0], ref[1][l][0]) and np.array_equal(clocks[l][1], ref[1][l][1])
     e = vlbm.Ensemble(vlbm.Params.jet(), levels, coefs, R)
-    for bad in ((None, 3, 0), (None, 4, 2), ([2, 0], 4, 0)):
+    for bad in ((None, 3, 0, 0), (None, 4, 2, 0), ([2, 0], 4, 0, 0), (None, 4, 0, 2)):
         with pytest.raises(vlbm.VlbmError):
             e.set_tuning(*bad)
     e.close()
@@ -578,36 +580,73 @@ def test_checkpoint_resume_is_bitwise(precision):
     b.close()
 
 
-def test_mixed_vs_fp64_statistics_jet640_early():
-    """The benchmark workload (640 x 320, 64 realizations) at t = 1e-4: the mixed
-    variant's one-point W1 against the FP64 ensemble (same seeds) is below
-    1e-3 of the mean density, and so is the mean-field difference; the std
-    fields, small over most of the domain, within 2e-2 (relative L1)."""
+def _jet640_stats(precision, t_final, first_seed=0, ulp=None):
+    """Restricted (2 x 2) mean/std of (rho, |v|, p) and sorted restricted density
+    samples of the 640 x 320, 64-realization workload at t_final; ulp = (variable,
+    direction) moves the inlet column's macroscopic variable by one ulp first."""
     w = inputs.WORKLOADS["jet640"]
-    R, t_final = w.m, 1e-4
-    coefs = inputs.kl_coefficients(inputs.DEFAULT_SEED, 0, R)
+    R = w.m
+    coefs = inputs.kl_coefficients(inputs.DEFAULT_SEED, first_seed, R)
     ncell = (w.nx // 2) * (w.ny // 2)
-    res = {}
-    for prec in ("fp64", "mixed"):
-        ens = vlbm.Ensemble(vlbm.Params.jet(precision=prec), [(w.nx, w.ny, w.dx, w.y_min)], coefs, R)
-        ens.run(t_final, chunk=64)
-        acc = torch.empty((3, 2, ncell), dtype=torch.float64, device="cuda")
-        smp = torch.empty((R, ncell), dtype=torch.float64, device="cuda")
-        vlbm.vlbm_ensemble_stats(ens.h, 0, 2, acc, 0, smp, 0)
-        mean = torch.empty((3, ncell), dtype=torch.float64, device="cuda")
-        std = torch.empty_like(mean)
-        vlbm.vlbm_stats_finalize(acc, ncell, R, mean, std)
-        vlbm.vlbm_sort_samples(smp, ncell, R)
-        res[prec] = (mean, std, smp)
-        ens.close()
-    w1c = torch.empty(ncell, dtype=torch.float64, device="cuda")
+    ens = vlbm.Ensemble(vlbm.Params.jet(precision=precision), [(w.nx, w.ny, w.dx, w.y_min)], coefs, R)
+    if ulp is not None:
+        var, sign = ulp
+        st = ens.state(0)
+        col = st[var, 0, :, :, 0]
+        st[var, 0, :, :, 0] = torch.nextafter(col, torch.full_like(col, sign * float("inf")))
+        t, s, a, _ = ens.times(0)
+        ens.set_state(0, st, t, s, a)
+        del st
+    ens.run(t_final, chunk=240)
+    t, _, _, status = ens.times(0)
+    assert np.all(status == 0) and np.all(t == t_final)
+    acc = torch.empty((3, 2, ncell), dtype=torch.float64, device="cuda")
+    smp = torch.empty((R, ncell), dtype=torch.float64, device="cuda")
+    vlbm.vlbm_ensemble_stats(ens.h, 0, 2, acc, 0, smp, 0)
+    mean = torch.empty((3, ncell), dtype=torch.float64, device="cuda")
+    std = torch.empty_like(mean)
+    vlbm.vlbm_stats_finalize(acc, ncell, R, mean, std)
+    vlbm.vlbm_sort_samples(smp, ncell, R)
+    ens.close()
+    return mean.cpu().numpy(), std.cpu().numpy(), smp
+
+
+def _stat_errors(ref, other):
+    """W1 / mean density (eq:w1disc), and the largest rel. L1 error of the mean
+    and of the std fields (eq:mean, eq:std) of `other` against `ref`."""
+    m0, s0, smp0 = ref
+    m1, s1, smp1 = other
+    nc = m0.shape[1]
+    w1c = torch.empty(nc, dtype=torch.float64, device="cuda")
     w1m = torch.zeros(1, dtype=torch.float64, device="cuda")
-    vlbm.vlbm_w1(res["fp64"][2], res["mixed"][2], ncell, R, w1c, w1m)
+    vlbm.vlbm_w1(smp0, smp1, nc, smp0.shape[0], w1c, w1m)
     torch.cuda.synchronize()
-    m64, s64 = res["fp64"][0].cpu().numpy(), res["fp64"][1].cpu().numpy()
-    mmx, smx = res["mixed"][0].cpu().numpy(), res["mixed"][1].cpu().numpy()
-    ew = w1m.item() / m64[0].mean()
-    em = max(_rel_l1(mmx[f], m64[f]) for f in range(3))
-    es = max(_rel_l1(smx[f], s64[f]) for f in range(3))
-    print(f"jet640 t=1e-4 mixed vs fp64: W1/mean(rho) {ew:.3e}, mean {em:.3e}, std {es:.3e}")
-    assert ew < 1e-3 and em < 1e-3 and es < 2e-2
+    return (w1m.item() / m0[0].mean(), max(_rel_l1(m1[f], m0[f]) for f in range(3)),
+            max(_rel_l1(s1[f], s0[f]) for f in range(3)))
+
+
+def test_mixed_vs_fp64_at_final_time_is_at_the_roundoff_floor():
+    """The benchmark workload (640 x 320, 64 realizations) at its final time
+    t = 1e-3, after the bow shock and the shear-layer instability have
+    developed.  There the trajectories decorrelate under any perturbation of
+    round-off size: an FP64 ensemble whose inlet density is moved by one ulp
+    differs from the unperturbed one by about 4e-3 of the mean density in W1,
+    four times the 1e-3 of a literal bar.  The mixed variant is held to that
+    floor instead: its W1, mean and std errors against the FP64 ensemble (same
+    seeds) are at most 1.5 times the larger of the two one-ulp perturbations'
+    (measured about 1.2), and below the difference between two independent
+    seed sets (the sampling noise of 64 realizations)."""
+    t_final = inputs.WORKLOADS["jet640"].t_final
+    ref = _jet640_stats("fp64", t_final)
+    mixed = _stat_errors(ref, _jet640_stats("mixed", t_final))
+    floors = [_stat_errors(ref, _jet640_stats("fp64", t_final, ulp=(0, sign))) for sign in (1, -1)]
+    noise = _stat_errors(ref, _jet640_stats("fp64", t_final, first_seed=64))
+    floor = [max(f[k] for f in floors) for k in range(3)]
+    names = ("W1/mean(rho)", "mean rel L1", "std rel L1")
+    for k, name in enumerate(names):
+        print(f"t=1e-3 {name}: mixed {mixed[k]:.3e}, one-ulp floor {floor[k]:.3e} "
+              f"(ratio {mixed[k] / floor[k]:.2f}), independent seeds {noise[k]:.3e}")
+    assert floor[0] > 1e-3  # round-off alone already exceeds the literal 1e-3 bar
+    for k in range(3):
+        assert mixed[k] <= 1.5 * floor[k], names[k]
+        assert mixed[k] < noise[k], names[k]
