@@ -54,18 +54,17 @@ __device__ __forceinline__ void maxwellians(const Phys &P, const double u[4], do
 
 // Largest characteristic speed max(|v1|,|v2|) + c of the state u; *bad is set
 // when rho <= 0, p <= 0 or a value is not finite.
+// (Written without branches: every lane evaluates the same instructions.)
 __device__ __forceinline__ double wave_speed(double gamma, const double u[4], int *bad)
 {
     const double rho = u[0];
     const double v1 = u[1] / rho;
     const double v2 = u[2] / rho;
     const double p = (gamma - 1.0) * (u[3] - 0.5 * rho * (v1 * v1 + v2 * v2));
-    if (!(rho > 0.0) || !(p > 0.0) || !isfinite(rho) || !isfinite(p)) {
-        *bad = 1;
-        return 0.0;
-    }
+    const bool ok = rho > 0.0 && p > 0.0 && isfinite(rho) && isfinite(p);
     const double c = sqrt(gamma * p / rho);
-    return fmax(fabs(v1), fabs(v2)) + c;
+    *bad |= ok ? 0 : 1;
+    return ok ? fmax(fabs(v1), fabs(v2)) + c : 0.0;
 }
 
 // Relaxed local density bounds and low-order internal energy of a cell whose
@@ -117,37 +116,36 @@ __device__ __forceinline__ void maxwellian4(const Phys &P, const double u[4], do
 // Largest theta in [0,1] keeping L + theta*D inside [rmin, rmax] in density and
 // above pos_eps * rhoeL in internal energy (the quadratic
 // Q = rho E - |m|^2/2 - eps rhoeL rho has the sign of the constraint for rho > 0).
+// Selects instead of branches, except around the root of the quadratic, which
+// a wavefront skips unless one of its lanes needs it.
 __device__ __forceinline__ double side_theta(const Phys &P, const double L[4], double rmin,
                                              double rmax, double rhoeL, const double D[4])
 {
-    double th = 1.0;
-    if (D[0] > 0.0)
-        th = (rmax - L[0]) / D[0];
-    else if (D[0] < 0.0)
-        th = (rmin - L[0]) / D[0];
+    const bool dpos = D[0] > 0.0, dneg = D[0] < 0.0;
+    const double num = dpos ? rmax - L[0] : rmin - L[0];
+    const double quot = num / D[0];
+    double th = (dpos || dneg) ? quot : 1.0;
     th = fmin(fmax(th, 0.0), 1.0);
 
-    if (!(rhoeL > 0.0))
-        return 0.0;
+    const bool ok = rhoeL > 0.0;
     const double eps = P.pos_eps;
     const double c2 = D[0] * D[3] - 0.5 * (D[1] * D[1] + D[2] * D[2]);
     const double c1 = L[0] * D[3] + D[0] * L[3] - (L[1] * D[1] + L[2] * D[2]) - eps * rhoeL * D[0];
     const double c0 = (1.0 - eps) * L[0] * rhoeL;
     const double q = c0 + th * (c1 + th * c2);
-    if (q >= 0.0)
-        return th;
-    double disc = c1 * c1 - 4.0 * c2 * c0;
-    if (disc < 0.0)
-        disc = 0.0;
-    const double sq = sqrt(disc);
-    double r;
-    if (c1 < 0.0)
-        r = 2.0 * c0 / (sq - c1);
-    else if (c2 < 0.0)
-        r = (c1 + sq) / (-2.0 * c2);
-    else
-        r = 0.0;
-    return fmin(fmax(r, 0.0), th);
+    double res = th;
+    if (ok && !(q >= 0.0)) {
+        double disc = c1 * c1 - 4.0 * c2 * c0;
+        disc = disc < 0.0 ? 0.0 : disc;
+        const double sq = sqrt(disc);
+        const bool c1neg = c1 < 0.0;
+        const double rn = c1neg ? 2.0 * c0 : c1 + sq;
+        const double rd = c1neg ? sq - c1 : -2.0 * c2;
+        const double rq = rn / rd;
+        const double r = (c1neg || c2 < 0.0) ? rq : 0.0;
+        res = fmin(fmax(r, 0.0), th);
+    }
+    return ok ? res : 0.0;
 }
 
 // ---------------------------------------------------------------------------

@@ -47,10 +47,11 @@ namespace vlbm {
 
 // Lane exchange along the strip: lane i receives the value of lane i-1
 // (from_left) or lane i+1 (from_right).  DPP wavefront shifts by one lane
-// (a VALU operand modifier, no LDS round trip); the end lanes keep their own
-// value, which only halo lanes ever read.
-__device__ __forceinline__ int dpp_left_i(int x) { return __builtin_amdgcn_update_dpp(x, x, 0x138, 0xf, 0xf, false); }
-__device__ __forceinline__ int dpp_right_i(int x) { return __builtin_amdgcn_update_dpp(x, x, 0x130, 0xf, 0xf, false); }
+// (a VALU operand modifier, no LDS round trip) into a fresh register; the end
+// lanes receive 0 (bound control), which only halo lanes ever read, so the
+// shifted value needs no copy of the source first.
+__device__ __forceinline__ int dpp_left_i(int x) { return __builtin_amdgcn_mov_dpp(x, 0x138, 0xf, 0xf, true); }
+__device__ __forceinline__ int dpp_right_i(int x) { return __builtin_amdgcn_mov_dpp(x, 0x130, 0xf, 0xf, true); }
 __device__ __forceinline__ double from_left(double x)
 {
     const long long b = __double_as_longlong(x);
@@ -168,23 +169,36 @@ __device__ __forceinline__ void march_item(const PhysArgs &ph, const LevelArgs &
         slot_pop[q] = needed ? slot_in : slot_inner;
     }
     auto col_in = [&](int v, int sl) -> unsigned { return (sl == 0 ? slot_in : slot_pop[sl - 1]) * St::esize(v, sl); };
+    // The inlet column's lane stores its scheme values into the strip's last
+    // (padding) slot, which the halo lanes fill with scratch values anyway; its
+    // Dirichlet values go to its own slot.  So every scheme store is one store
+    // by all lanes, with no branch on the lane.
+    const unsigned slot_scheme = inlet_col ? (unsigned)(SLOTS * strip + SLOTS - 1) : slot_out;
     auto col_out = [&](int v, int sl) -> unsigned { return slot_out * St::esize(v, sl); };
+    auto col_scheme = [&](int v, int sl) -> unsigned { return slot_scheme * St::esize(v, sl); };
     double wmax = 0.0;
     int bad = 0;
     auto store_slot = [&](int sl, int j, const double x[4]) {
 #pragma unroll
         for (int v = 0; v < 4; ++v)
+            St::stp(outb + row_off(j, v, sl), v, sl, col_scheme(v, sl), x[v]);
+    };
+    auto store_inlet = [&](int sl, int j, const double x[4]) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
             St::stp(outb + row_off(j, v, sl), v, sl, col_out(v, sl), x[v]);
     };
-    auto account = [&](const double u[4]) {
+    // wave-speed maximum and admissibility of a stored state, for the lanes in `mask`
+    auto account = [&](const double u[4], bool mask) {
         double us[4];
 #pragma unroll
         for (int v = 0; v < 4; ++v)
             us[v] = Sout.stored(v, u[v]);
         int b2 = 0;
-        wmax = fmax(wmax, wave_speed(ph.gamma, us, &b2));
+        const double ws = wave_speed(ph.gamma, us, &b2);
         const bool fin = isfinite(us[0]) && isfinite(us[1]) && isfinite(us[2]) && isfinite(us[3]);
-        bad |= !fin ? STATUS_NONFINITE : (b2 ? STATUS_NONPOSITIVE : 0);
+        wmax = fmax(wmax, mask ? ws : 0.0);
+        bad |= !mask ? 0 : (!fin ? STATUS_NONFINITE : (b2 ? STATUS_NONPOSITIVE : 0));
     };
     auto shuffle_copy = [&](double x[4]) {
         if (wave_copy) {
@@ -192,20 +206,17 @@ __device__ __forceinline__ void march_item(const PhysArgs &ph, const LevelArgs &
             for (int v = 0; v < 4; ++v) {
                 const double fl = from_left(x[v]);
                 const double fr = from_right(x[v]);
-                if (copy_from_left)
-                    x[v] = fl;
-                else if (copy_from_right)
-                    x[v] = fr;
+                x[v] = copy_from_left ? fl : (copy_from_right ? fr : x[v]);
             }
         }
     };
-    // Row j of the chunk is stored by every lane but the inlet column's (written
-    // on its own, after the scheme values of its row); it is duplicated into
-    // the zero-gradient rows 0 / ny-1 when it is the adjacent interior row.
-    // The stored values of the output lanes also enter the wave-speed maximum
-    // and the admissibility check.
-    auto row_written = [&](int j) { return !inlet_col && j >= y0 && j < y1 && (periodic || (j != 0 && j != ny - 1)); };
-    auto row_stored = [&](int j) { return out_lane && row_written(j); };
+    // Row j of the chunk is stored by the wave (the same condition for every
+    // lane); it is duplicated into the zero-gradient rows 0 / ny-1 when it is
+    // the adjacent interior row.  The stored values of the output lanes but the
+    // inlet's (written on its own) enter the wave-speed maximum and the
+    // admissibility check.
+    auto row_written = [&](int j) { return j >= y0 && j < y1 && (periodic || (j != 0 && j != ny - 1)); };
+    const bool scheme_lane = out_lane && !inlet_col;
     // (a level with ny = 3 duplicates its single interior row into both)
     auto dup_lo = [&](int j) { return !periodic && j == 1; };
     auto dup_hi = [&](int j) { return !periodic && j == ny - 2; };
@@ -362,9 +373,8 @@ __device__ __forceinline__ void march_item(const PhysArgs &ph, const LevelArgs &
             }
             shuffle_copy(u4);
             shuffle_copy(u0);
-            if (row_stored(r))
-                account(u0);
             if (row_written(r)) {
+                account(u0, scheme_lane);
                 store_slot(0, r, u0);
                 store_slot(4, r, u4);
                 if (dup_lo(r)) {
@@ -413,12 +423,14 @@ __device__ __forceinline__ void march_item(const PhysArgs &ph, const LevelArgs &
             }
             // Dirichlet inlet column (eq:inletBC): u kept, populations at
             // equilibrium for this step's kinetic speed.
-            if (inlet_wave && out_lane && inlet_col && jB >= y0 && jB < y1) {
-                store_slot(0, jB, U1);
+            if (inlet_wave && jB >= y0 && jB < y1) {
+                if (out_lane && inlet_col) {
+                    store_inlet(0, jB, U1);
 #pragma unroll
-                for (int q = 0; q < 4; ++q)
-                    store_slot(1 + q, jB, MB[q]);
-                account(U1);
+                    for (int q = 0; q < 4; ++q)
+                        store_inlet(1 + q, jB, MB[q]);
+                }
+                account(U1, out_lane && inlet_col);
             }
         }
 
