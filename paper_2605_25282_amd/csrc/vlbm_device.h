@@ -339,6 +339,18 @@ __device__ __forceinline__ StepCtl step_control(double t, double amax, double ka
 static constexpr int STRIP = 60;   // output columns per strip
 static constexpr int SLOTS = 64;   // element slots per strip in a plane row
 
+// Raw buffer resources of the step kernel: 64-bit base, no stride, bound
+// num_records, 32-bit data format (the descriptor word of untyped gfx9
+// buffers).  Accesses whose lane offset exceeds num_records are dropped
+// (stores) or read as 0 (loads).  Stores carry the non-temporal hint.
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+static constexpr int BUF_FORMAT_WORD = 0x00020000;
+static constexpr int BUF_NT = 2;
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t row_rsrc(const char *row, unsigned bytes)
+{
+    return __builtin_amdgcn_make_buffer_rsrc((void *)row, (short)0, (int)bytes, BUF_FORMAT_WORD);
+}
+
 // Strips per row: ceil(nx / 60), except that a bounded level whose last column
 // is 60 q + 60 lets the last strip's lane 62 carry it (that column is a copy of
 // its left neighbour, which the same wave computes).
@@ -394,6 +406,21 @@ struct StateFP64 {
         return *(const unsigned long long *)(base + off);
     }
     __device__ static __forceinline__ double decode(int, int, unsigned long long r) { return __longlong_as_double((long long)r); }
+    // Buffer forms used by the step kernel: `rsrc` covers one row block, voff is
+    // the lane's byte offset within a plane row, soff the plane's offset.
+    __device__ static __forceinline__ unsigned long long ldbuf(__amdgpu_buffer_rsrc_t rsrc, int, int, unsigned voff,
+                                                               unsigned soff)
+    {
+        const u32x2 r = __builtin_amdgcn_raw_buffer_load_b64(rsrc, (int)voff, (int)soff, 0);
+        return ((unsigned long long)r.y << 32) | r.x;
+    }
+    __device__ static __forceinline__ void stbuf(__amdgpu_buffer_rsrc_t rsrc, int, int, unsigned voff, unsigned soff,
+                                                 double x)
+    {
+        const unsigned long long b = (unsigned long long)__double_as_longlong(x);
+        const u32x2 d = {(unsigned)(b & 0xffffffffull), (unsigned)(b >> 32)};
+        __builtin_amdgcn_raw_buffer_store_b64(d, rsrc, (int)voff, (int)soff, BUF_NT);
+    }
 };
 
 struct StateMixed {
@@ -458,6 +485,25 @@ struct StateMixed {
         if (is_f32(v, s))
             return (double)__uint_as_float((unsigned int)r);
         return __longlong_as_double((long long)r);
+    }
+    __device__ static __forceinline__ unsigned long long ldbuf(__amdgpu_buffer_rsrc_t rsrc, int v, int s, unsigned voff,
+                                                               unsigned soff)
+    {
+        if (is_f32(v, s))
+            return (unsigned long long)__builtin_amdgcn_raw_buffer_load_b32(rsrc, (int)voff, (int)soff, 0);
+        const u32x2 r = __builtin_amdgcn_raw_buffer_load_b64(rsrc, (int)voff, (int)soff, 0);
+        return ((unsigned long long)r.y << 32) | r.x;
+    }
+    __device__ static __forceinline__ void stbuf(__amdgpu_buffer_rsrc_t rsrc, int v, int s, unsigned voff, unsigned soff,
+                                                 double x)
+    {
+        if (is_f32(v, s)) {
+            __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint((float)x), rsrc, (int)voff, (int)soff, BUF_NT);
+            return;
+        }
+        const unsigned long long b = (unsigned long long)__double_as_longlong(x);
+        const u32x2 d = {(unsigned)(b & 0xffffffffull), (unsigned)(b >> 32)};
+        __builtin_amdgcn_raw_buffer_store_b64(d, rsrc, (int)voff, (int)soff, BUF_NT);
     }
 };
 

@@ -120,7 +120,6 @@ __device__ __forceinline__ void march_item(const PhysArgs &ph, const LevelArgs &
     char *const outb = Sout.real_base(m);
     const unsigned pitch = Sin.pitch;
     const int W = Sin.W;
-    auto row_off = [&](int j, int v, int sl) -> size_t { return (size_t)((unsigned)j * pitch + St::poff(W, v, sl)); };
 
     // ---- geometry of this lane ----
     const int c = strip * STRIP - 2 + lane; // column
@@ -178,15 +177,22 @@ __device__ __forceinline__ void march_item(const PhysArgs &ph, const LevelArgs &
     auto col_scheme = [&](int v, int sl) -> unsigned { return slot_scheme * St::esize(v, sl); };
     double wmax = 0.0;
     int bad = 0;
+    // Every access goes through a buffer resource of one row block (uniform, in
+    // scalar registers): the lane's column offset is the vector offset, the
+    // plane's offset within the row block the scalar offset.
+    auto out_row = [&](int j) { return row_rsrc(outb + (size_t)((unsigned)j * pitch), pitch); };
+    auto in_row = [&](int j) { return row_rsrc(inb + (size_t)((unsigned)j * pitch), pitch); };
     auto store_slot = [&](int sl, int j, const double x[4]) {
+        const __amdgpu_buffer_rsrc_t rj = out_row(j);
 #pragma unroll
         for (int v = 0; v < 4; ++v)
-            St::stp(outb + row_off(j, v, sl), v, sl, col_scheme(v, sl), x[v]);
+            St::stbuf(rj, v, sl, col_scheme(v, sl), St::poff(W, v, sl), x[v]);
     };
     auto store_inlet = [&](int sl, int j, const double x[4]) {
+        const __amdgpu_buffer_rsrc_t rj = out_row(j);
 #pragma unroll
         for (int v = 0; v < 4; ++v)
-            St::stp(outb + row_off(j, v, sl), v, sl, col_out(v, sl), x[v]);
+            St::stbuf(rj, v, sl, col_out(v, sl), St::poff(W, v, sl), x[v]);
     };
     // wave-speed maximum and admissibility of a stored state, for the lanes in `mask`
     auto account = [&](const double u[4], bool mask) {
@@ -250,14 +256,15 @@ __device__ __forceinline__ void march_item(const PhysArgs &ph, const LevelArgs &
     auto urow = [&](int k) { return row_of(min(k, k_last)); };
     auto load_x = [&](int k, double (&Ux)[4], unsigned long long (&Px)[4][4]) {
         const int ju = urow(k), jp = prow(k);
+        const __amdgpu_buffer_rsrc_t ru = in_row(ju), rp = in_row(jp);
 #pragma unroll
         for (int v = 0; v < 4; ++v)
-            Ux[v] = St::ldp(inb + row_off(ju, v, 0), v, 0, col_in(v, 0));
+            Ux[v] = St::decode(v, 0, St::ldbuf(ru, v, 0, col_in(v, 0), St::poff(W, v, 0)));
 #pragma unroll
         for (int q = 0; q < 4; ++q)
 #pragma unroll
             for (int v = 0; v < 4; ++v)
-                Px[q][v] = St::ldraw(inb + row_off(jp, v, 1 + q), v, 1 + q, col_in(v, 1 + q));
+                Px[q][v] = St::ldbuf(rp, v, 1 + q, col_in(v, 1 + q), St::poff(W, v, 1 + q));
     };
     // an even number of iterations (a leading one on rows that are never stored
     // when chunk + 4 is odd), so the two buffers alternate without a join
