@@ -113,6 +113,37 @@ def test_largest_level_two_realizations():
         assert _plane_err(got[m], ref[m]) <= TOL, m
 
 
+def test_headline_pair_is_independent_of_the_decomposition():
+    """The benchmark's 5056x2528 + 2528x1264 pair (8 realizations here), 30
+    steps of one launch per step under the work-queue dealing with the default
+    items, the static round-robin dealing with 632-row items, and the work
+    queues with the tuned 33 / 32-row items on blocks of one wavefront: the
+    states of both levels are equal bit for bit (compared on the device)."""
+    fine = inputs.WORKLOADS["jet5056"]
+    works = [(fine.nx // 2, fine.ny // 2), (fine.nx, fine.ny)]
+    levels = [(nx, ny, 1.0 / nx, -0.25) for nx, ny in works]
+    R, steps = 8, 30
+    coefs = inputs.kl_coefficients(inputs.DEFAULT_SEED, 0, R)
+    ref = None
+    for chunks, wpb, order, deal in ((None, 4, 0, 1), ([632, 632], 4, 0, 0), ([33, 32], 1, 0, 1)):
+        ens = vlbm.Ensemble(vlbm.Params.jet(), levels, coefs, R)
+        ens.set_tuning(chunks, wpb, order, deal)
+        ens.step(1e30, steps)
+        for l in range(2):
+            t, s, a, status = ens.times(l)
+            assert np.all(s == steps) and np.all(status == 0)
+        states = [ens.state(l) for l in range(2)]
+        ens.close()
+        del ens
+        if ref is None:
+            ref = states
+        else:
+            for l in range(2):
+                assert torch.equal(states[l], ref[l]), (chunks, wpb, order, deal, l)
+        del states
+        torch.cuda.empty_cache()
+
+
 def test_batched_statistics_equal_one_batch():
     """An ensemble streamed in two batches (accumulators merged with n_prev,
     samples scattered at m_offset) gives the statistics of the whole ensemble
