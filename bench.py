@@ -127,6 +127,15 @@ def cpu_baseline(name, nx, ny, dx, y_min, steps=None, seconds_target: float = 15
                       f"{lups:.3e} node updates)"}
 
 
+def decomposition(vlbm, h, n_levels: int, autotuned: bool) -> dict:
+    """The step kernel's decomposition in use on handle h (vlbm_get_tuning)."""
+    chunks, wpb, order, deal = vlbm.vlbm_get_tuning(h, n_levels)
+    return {"rows_per_wave": chunks, "waves_per_block": wpb,
+            "item_order": "strip fastest" if order == 0 else "realization fastest",
+            "dealing": "static round-robin" if deal == 0 else "per-XCD work queues",
+            "autotuned": autotuned}
+
+
 def progress(msg: str) -> None:
     """One line per finished stage on stderr (stdout carries only the JSON line)."""
     print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
@@ -598,9 +607,10 @@ def run_pass(args, torch, vlbm, inputs) -> int:
         tune = tune and not args.no_tune
         if tune:
             h = vlbm.vlbm_init_ensemble(params, [level], coefs, R, stream)
-            tuned = vlbm.vlbm_autotune(h, w.t_final, 4, 1)
+            vlbm.vlbm_autotune(h, w.t_final, 4, 1)
+            tuned = [decomposition(vlbm, h, 1, True)]
             vlbm.vlbm_destroy(h)
-            progress(f"{precision}: autotuned {tuned[0]} rows per wave")
+            progress(f"{precision}: step kernel decomposition {tuned[0]}")
         n_timed = args.steps if timed_steps is None else timed_steps
         n_warm = args.warmup if warmup is None else warmup
         step_ms, step_launches, totals = [0.0], [0], {"lups": 0.0}
@@ -709,7 +719,7 @@ def run_pass(args, torch, vlbm, inputs) -> int:
                    "precision": head, "nx": w.nx, "ny": w.ny, "realizations": R,
                    "t_final": w.t_final, "seed": inputs.DEFAULT_SEED,
                    "time_steps_per_realization": r0["steps"],
-                   "step_kernel_rows_per_wave": r0["tuned_rows"],
+                   "step_kernel_decomposition": r0["tuned_rows"],
                    "phases_ms_per_step": r0["phases_ms"]},
         "roofline": {"bound": "hbm", "achieved": round(r0["achieved"], 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(r0["achieved"] / HBM_PEAK_GBS, 4),
@@ -795,7 +805,7 @@ def run_pass(args, torch, vlbm, inputs) -> int:
             "fp64_independent_ensemble_difference": stat_errors(res["fp64"], other),
             "error_vs_fp64_earlier_times": early,
             "time_steps_per_realization": rm["steps"],
-            "step_kernel_rows_per_wave": rm["tuned_rows"],
+            "step_kernel_decomposition": rm["tuned_rows"],
             "phases_ms_per_step": rm["phases_ms"],
         }
         add_hbm(out["mixed"]["roofline"], "mixed")
@@ -833,7 +843,8 @@ def run_study(args, torch, vlbm, inputs) -> int:
     tuned = None
     if not args.no_tune:
         ens = vlbm.Ensemble(params, levels, coefs, R)
-        tuned = ens.autotune(checkpoints[0], 4)
+        ens.autotune(checkpoints[0], 4)
+        tuned = decomposition(vlbm, ens.h, len(levels), True)
         ens.close()
         del ens  # release the tuning ensemble's state before the measured one allocates its own
     ens = vlbm.Ensemble(params, levels, coefs, R)
@@ -877,7 +888,7 @@ def run_study(args, torch, vlbm, inputs) -> int:
         "config": {"workload": f"nested levels of the Mach-2000 jet ({grids} on {geometry}), M={R} "
                                f"realizations each with the same seeds, to t={checkpoints[-1]:g}, one "
                                f"launch per step of all levels, {precision}",
-                   "launches": launches, "step_kernel_rows_per_wave": tuned},
+                   "launches": launches, "step_kernel_decomposition": tuned},
         "roofline": {"bound": "hbm", "achieved": round(bpl * lups / step_s / 1e9, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(bpl * lups / step_s / 1e9 / HBM_PEAK_GBS, 4),
                      "traffic": None, "kernel": "vlbm step kernel (all levels per launch)",
@@ -1061,7 +1072,8 @@ def run_c5(args, torch, vlbm, inputs) -> int:
         coefs = inputs.kl_coefficients(inputs.DEFAULT_SEED, b * Mb, Mb)
         ens = vlbm.Ensemble(params, levels, coefs, Mb)
         if b == 0 and not args.no_tune:
-            tuned = ens.autotune(fine.t_final, 4)  # live steps, cached for later batches
+            ens.autotune(fine.t_final, 4)  # live steps, cached for later batches
+            tuned = decomposition(vlbm, ens.h, 2, True)
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
         e0.record(stream)
@@ -1107,7 +1119,7 @@ def run_c5(args, torch, vlbm, inputs) -> int:
         "config": {"workload": f"largest level 5056x2528 with 2528x1264 on the same seeds, {B} batches of "
                                f"{Mb} realizations streamed to t={fine.t_final:g} (the study's M = 1000 "
                                f"would be {1000 // Mb} such batches), {precision}",
-                   "launches": launches, "step_kernel_rows_per_wave": tuned,
+                   "launches": launches, "step_kernel_decomposition": tuned,
                    "extrapolated_s_for_m1000": round(elapsed / M * 1000, 1)},
         "roofline": {"bound": "hbm", "achieved": round(bpl * lups / step_s / 1e9, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(bpl * lups / step_s / 1e9 / HBM_PEAK_GBS, 4),
