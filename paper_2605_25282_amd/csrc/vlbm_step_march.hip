@@ -19,9 +19,13 @@
 // the low-order state and the Maxwellians of the newest row travel to the
 // next iteration.  x-neighbours are exchanged with DPP lane shifts.  Each
 // value of the state is read from memory once (plus the 2-column and 2-row
-// halos of the stencil) and written once, each store instruction covering
-// the strip's whole 64-slot block of a plane row (see the layout in
-// vlbm_device.h): 320 B per FP64 node update.
+// halos of the stencil; the halo lanes read a neighbouring strip only where
+// the stencil uses it) and written once, each store instruction covering the
+// strip's whole 64-slot block of a plane row (see the layout in
+// vlbm_device.h): 320 B per FP64 node update.  Loads and stores go through
+// raw buffer resources of one row block, so addresses are a scalar base and
+// plane offset plus one loop-invariant lane offset; stores and the limiter's
+// side conditions are lane-uniform or selects, so the loop has few branches.
 //
 // Every arithmetic expression has the operand order of the reference form in
 // vlbm_kernels.hip (and of the oracle), so the result is bitwise identical.
@@ -30,11 +34,10 @@
 // rows) are produced by the wave that owns the copied interior node.
 //
 // Work items (realization, row chunk, strip) of every mesh level are ordered
-// strip-fastest (or realization-fastest, a tuning choice) and dealt
-// round-robin to a grid of blocks of 1, 2 or 4 wavefronts sized to the
-// resident capacity of the chip; blocks are renumbered so that consecutive
-// items land on one XCD (shared L2 for the halo re-reads of neighbouring
-// strips).
+// strip-fastest (or realization-fastest, a tuning choice) and given to a
+// persistent grid of blocks of 1, 2 or 4 wavefronts sized to the resident
+// capacity of the chip, either through per-XCD work queues (the default) or
+// round-robin; both keep neighbouring strips on one XCD's L2.
 #include "vlbm_device.h"
 
 namespace vlbm {
