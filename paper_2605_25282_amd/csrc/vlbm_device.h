@@ -116,10 +116,18 @@ __device__ __forceinline__ void maxwellian4(const Phys &P, const double u[4], do
 // Largest theta in [0,1] keeping L + theta*D inside [rmin, rmax] in density and
 // above pos_eps * rhoeL in internal energy (the quadratic
 // Q = rho E - |m|^2/2 - eps rhoeL rho has the sign of the constraint for rho > 0).
-// Selects instead of branches, except around the root of the quadratic, which
-// a wavefront skips unless one of its lanes needs it.
-__device__ __forceinline__ double side_theta(const Phys &P, const double L[4], double rmin,
-                                             double rmax, double rhoeL, const double D[4])
+// In two parts: side_main takes the density bound and evaluates the quadratic
+// at it (selects, no branches); only where Q is negative there does side_root
+// solve the quadratic for its root.  A caller that needs several sides can
+// evaluate all their main parts in one stretch of straight-line code and then
+// take the (rarely needed) roots, so the independent divisions interleave.
+struct SideTheta {
+    double th, c0, c1, c2; // density-bounded theta, coefficients of Q(theta)
+    bool ok;               // rhoeL > 0 (otherwise theta = 0)
+    bool root;             // Q(th) < 0: the root of Q bounds theta
+};
+__device__ __forceinline__ SideTheta side_main(const Phys &P, const double L[4], double rmin, double rmax,
+                                               double rhoeL, const double D[4])
 {
     const bool dpos = D[0] > 0.0, dneg = D[0] < 0.0;
     const double num = dpos ? rmax - L[0] : rmin - L[0];
@@ -133,19 +141,34 @@ __device__ __forceinline__ double side_theta(const Phys &P, const double L[4], d
     const double c1 = L[0] * D[3] + D[0] * L[3] - (L[1] * D[1] + L[2] * D[2]) - eps * rhoeL * D[0];
     const double c0 = (1.0 - eps) * L[0] * rhoeL;
     const double q = c0 + th * (c1 + th * c2);
-    double res = th;
-    if (ok && !(q >= 0.0)) {
-        double disc = c1 * c1 - 4.0 * c2 * c0;
-        disc = disc < 0.0 ? 0.0 : disc;
-        const double sq = sqrt(disc);
-        const bool c1neg = c1 < 0.0;
-        const double rn = c1neg ? 2.0 * c0 : c1 + sq;
-        const double rd = c1neg ? sq - c1 : -2.0 * c2;
-        const double rq = rn / rd;
-        const double r = (c1neg || c2 < 0.0) ? rq : 0.0;
-        res = fmin(fmax(r, 0.0), th);
-    }
-    return ok ? res : 0.0;
+    return SideTheta{th, c0, c1, c2, ok, ok && !(q >= 0.0)};
+}
+// theta bounded by the smallest positive root of Q (only meaningful when s.root)
+__device__ __forceinline__ double side_root(const SideTheta &s)
+{
+    double disc = s.c1 * s.c1 - 4.0 * s.c2 * s.c0;
+    disc = disc < 0.0 ? 0.0 : disc;
+    const double sq = sqrt(disc);
+    const bool c1neg = s.c1 < 0.0;
+    const double rn = c1neg ? 2.0 * s.c0 : s.c1 + sq;
+    const double rd = c1neg ? sq - s.c1 : -2.0 * s.c2;
+    const double rq = rn / rd;
+    const double r = (c1neg || s.c2 < 0.0) ? rq : 0.0;
+    return fmin(fmax(r, 0.0), s.th);
+}
+// the limited theta of one side from its two parts
+__device__ __forceinline__ double side_value(const SideTheta &s, double root)
+{
+    return s.ok ? (s.root ? root : s.th) : 0.0;
+}
+__device__ __forceinline__ double side_theta(const Phys &P, const double L[4], double rmin,
+                                             double rmax, double rhoeL, const double D[4])
+{
+    const SideTheta s = side_main(P, L, rmin, rmax, rhoeL, D);
+    double root = s.th;
+    if (s.root)
+        root = side_root(s);
+    return side_value(s, root);
 }
 
 // ---------------------------------------------------------------------------

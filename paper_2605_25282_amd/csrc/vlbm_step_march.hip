@@ -311,8 +311,15 @@ __device__ __forceinline__ void march_item(const PhysArgs &ph, const LevelArgs &
                 LB[v] = P.alpha * U1[v] + M1w[v] + M2e[v] + M3C[v] + M4n[v];
             cell_bounds(P, LB, M1w[0], M2e[0], M3C[0], M4n[0], U1[0], &bB[0], &bB[1], &bB[2]);
         }
-        // theta of the east x-face of row k-1
-        double txB = 0.0;
+        // Blending parameters of the two faces this iteration settles: the east
+        // x-face of row k-1 and the y-face between rows k-2 and k-1, each the
+        // smallest theta its interior sides admit.  The main parts of all four
+        // sides are straight-line code evaluated on every lane (the results of
+        // sides that are not interior are never selected), so their divisions
+        // interleave; the root of the energy quadratic follows where a lane
+        // needs it.
+        const int r = k - 2;
+        double txB, tyC;
         {
             double Lr[4], br[3], N2r[4];
 #pragma unroll
@@ -323,54 +330,41 @@ __device__ __forceinline__ void march_item(const PhysArgs &ph, const LevelArgs &
 #pragma unroll
             for (int q = 0; q < 3; ++q)
                 br[q] = from_right(bB[q]);
-            const bool in1 = interior(jB);
-            const int in2 = from_right_i((int)in1);
-            if (in1 || in2) {
-                if (lim == LIM_ZERO) {
-                    txB = 0.0;
-                } else if (lim == LIM_ONE) {
-                    txB = 1.0;
-                } else {
-                    double Dup[4], Ddn[4];
+            const bool inx1 = interior(jB);
+            const bool inx2 = from_right_i((int)inx1) != 0;
+            const bool iny1 = interior(r), iny2 = inx1;
+            double Dxu[4], Dxd[4], Dyu[4], Dyd[4];
 #pragma unroll
-                    for (int v = 0; v < 4; ++v) {
-                        const double A = NB[0][v] - N2r[v];
-                        Dup[v] = -4.0 * A;
-                        Ddn[v] = 4.0 * A;
-                    }
-                    txB = 1.0;
-                    if (in1)
-                        txB = fmin(txB, side_theta(P, LB, bB[0], bB[1], bB[2], Dup));
-                    if (in2)
-                        txB = fmin(txB, side_theta(P, Lr, br[0], br[1], br[2], Ddn));
-                }
+            for (int v = 0; v < 4; ++v) {
+                const double A = NB[0][v] - N2r[v];
+                Dxu[v] = -4.0 * A;
+                Dxd[v] = 4.0 * A;
+                const double B = N3C[v] - NB[3][v];
+                Dyu[v] = -4.0 * B;
+                Dyd[v] = 4.0 * B;
             }
-        }
-        // theta of the y-face between rows k-2 and k-1
-        const int r = k - 2;
-        double tyC = 0.0;
-        {
-            const bool in1 = interior(r), in2 = interior(jB);
-            if (in1 || in2) {
-                if (lim == LIM_ZERO) {
-                    tyC = 0.0;
-                } else if (lim == LIM_ONE) {
-                    tyC = 1.0;
-                } else {
-                    double Dup[4], Ddn[4];
+            const SideTheta sd[4] = {side_main(P, LB, bB[0], bB[1], bB[2], Dxu),
+                                     side_main(P, Lr, br[0], br[1], br[2], Dxd),
+                                     side_main(P, LC, bC[0], bC[1], bC[2], Dyu),
+                                     side_main(P, LB, bB[0], bB[1], bB[2], Dyd)};
+            const bool use[4] = {inx1, inx2, iny1, iny2};
+            double th[4];
 #pragma unroll
-                    for (int v = 0; v < 4; ++v) {
-                        const double A = N3C[v] - NB[3][v];
-                        Dup[v] = -4.0 * A;
-                        Ddn[v] = 4.0 * A;
-                    }
-                    tyC = 1.0;
-                    if (in1)
-                        tyC = fmin(tyC, side_theta(P, LC, bC[0], bC[1], bC[2], Dup));
-                    if (in2)
-                        tyC = fmin(tyC, side_theta(P, LB, bB[0], bB[1], bB[2], Ddn));
-                }
+            for (int i = 0; i < 4; ++i) {
+                double root = sd[i].th;
+                if (use[i] && sd[i].root)
+                    root = side_root(sd[i]);
+                th[i] = side_value(sd[i], root);
             }
+            auto face = [&](bool in1, bool in2, double t1, double t2) {
+                double t = 1.0;
+                t = in1 ? fmin(t, t1) : t;
+                t = in2 ? fmin(t, t2) : t;
+                const double mode = lim == LIM_ZERO ? 0.0 : (lim == LIM_ONE ? 1.0 : t);
+                return (in1 || in2) ? mode : 0.0;
+            };
+            txB = face(inx1, inx2, th[0], th[1]);
+            tyC = face(iny1, iny2, th[2], th[3]);
         }
 
         // Finish row k-2 (eq:vlbm4 and eq:vlbm5): u_4 and the macroscopic state.
@@ -383,8 +377,9 @@ __device__ __forceinline__ void march_item(const PhysArgs &ph, const LevelArgs &
             }
             shuffle_copy(u4);
             shuffle_copy(u0);
+            // (outside the store branch, so its divisions join the straight-line code)
+            account(u0, scheme_lane && row_written(r));
             if (row_written(r)) {
-                account(u0, scheme_lane);
                 store_slot(0, r, u0);
                 store_slot(4, r, u4);
                 if (dup_lo(r)) {
