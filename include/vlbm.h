@@ -36,11 +36,13 @@
  *
  * State layout of one mesh level, in one state buffer: realization-major,
  * then row-major, each mesh row one contiguous block holding that row of all
- * 20 planes (var, slot); a plane row is W = 64 * nstrip elements wide, the
- * columns grouped in strips of 60 (column i in element slot 64 q + i - 60 q,
- * q = min(i / 60, nstrip - 1)), nstrip = ceil(nx / 60), or (nx - 1) / 60 for a
- * non-periodic level with (nx - 1) divisible by 60:
- *     FP64:  double st[R realizations][ny][4 var][5 slot][W]   (160 B per slot)
+ * 20 planes (var, slot).  The columns are grouped in strips of 60: column i
+ * belongs to strip q = min(i / 60, nstrip - 1) at position t = i - 60 q
+ * (0..63), nstrip = ceil(nx / 60), or (nx - 1) / 60 for a non-periodic level
+ * with (nx - 1) divisible by 60; a row block is its nstrip strip blocks one
+ * after another, and a strip block holds 64 element positions of every plane:
+ *     FP64:  double st[R realizations][ny][nstrip][5 slot][4 var][64]
+ *            (10240 B per strip block, 160 B per position)
  * var = (rho, rho v1, rho v2, E); slot 0 is the macroscopic state u, slots
  * 1..4 are the populations u_1..u_4 (u_5 is eliminated, Sec. 2.1).  Node
  * (i, j) sits at x = (i + 1/2) dx, y = y_min + (j + 1/2) dx.  The unused slots
@@ -49,9 +51,9 @@
  * count, so read states only through vlbm_get_state, vlbm_moments or
  * vlbm_ensemble_stats.
  * With VLBM_MIXED the populations' rho, rho v1, rho v2 are stored in FP32 and
- * everything else in FP64; the row block of (realization, row) holds
- * double u[4 var][W], double E_k[4 slot][W], then float q[3 var][4 slot][W]
- * (112 B per slot).  All arithmetic, the pressure recovery and the
+ * everything else in FP64; a strip block holds double u[4 var][64],
+ * double E_k[4 slot][64], then float q[4 slot][3 var][64] (7168 B, 112 B per
+ * position).  All arithmetic, the pressure recovery and the
  * admissibility check are FP64.
  * One realization's state must stay below 4 GiB (about 24.9 M nodes in FP64,
  * 35.5 M in mixed precision, for nx a multiple of 60); larger levels are

@@ -350,17 +350,21 @@ __device__ __forceinline__ StepCtl step_control(double t, double amax, double ka
 // (input and output buffer) instead of 40 planes far apart, and all of a
 // realization's state lies within 4 GiB of its first byte, so kernels address
 // it with one 64-bit base and 32-bit offsets.
-// Within a plane row the columns are grouped by the step kernel's strips: strip
-// q (columns 60q .. 60q+59, the last strip also column 60q+60 when that is the
-// last column of a bounded level) occupies the 64 element slots 64q .. 64q+63,
-// so the wave of a strip writes whole 128-byte lines (the unused slots take
-// whatever its halo lanes hold); plane rows are 64 * nstrip elements wide.
-//   FP64:  plane (v, s) at element offset (v * 5 + s) * W of the row block,
-//          W = 64 * nstrip, pitch = 160 * W bytes.
-//   mixed: FP64 rows first (u, 4 variables, then E of slots 1..4), then the
-//          FP32 rows of rho, rho v1, rho v2 of slots 1..4; pitch = 112 * W.
+// Within a row block the columns are grouped by the step kernel's strips:
+// strip q (columns 60q .. 60q+59, the last strip also column 60q+60 when that
+// is the last column of a bounded level) owns element slots 0..63 of a strip
+// block, and the row block is its nstrip strip blocks one after another.  A
+// strip block holds all 20 planes of its 64 slots, each plane one run of 64
+// elements, so the wave of a strip reads and writes whole 128-byte lines (the
+// unused slots take whatever its halo lanes hold) and every plane sits at a
+// compile-time offset within the block:
+//   FP64:  double [5 slot][4 var][64]                 10240 B per strip block
+//   mixed: double u[4 var][64], double E[4 slot][64],
+//          float q[4 slot][3 var][64] (rho, rho v1, rho v2)   7168 B
+// A column's "slot index" is 64 q + (i - 60 q); its byte offset within the
+// row block is q * (strip block) + (i - 60 q) * (element size).
 static constexpr int STRIP = 60;   // output columns per strip
-static constexpr int SLOTS = 64;   // element slots per strip in a plane row
+static constexpr int SLOTS = 64;   // element slots per strip block and plane
 
 // Raw buffer resources of the step kernel: 64-bit base, no stride, bound
 // num_records, 32-bit data format (the descriptor word of untyped gfx9
@@ -373,6 +377,11 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t row_rsrc(const char *row, unsi
 {
     return __builtin_amdgcn_make_buffer_rsrc((void *)row, (short)0, (int)bytes, BUF_FORMAT_WORD);
 }
+// A plane offset (a compile-time constant) is split into the instruction's
+// 12-bit immediate (added to the lane offset) and a multiple of 4096 in the
+// scalar offset, so no register holds it.
+__device__ __forceinline__ int buf_voff(unsigned lane_off, unsigned plane_off) { return (int)(lane_off + (plane_off & 4095u)); }
+__device__ __forceinline__ int buf_soff(unsigned plane_off) { return (int)(plane_off & ~4095u); }
 
 // Strips per row: ceil(nx / 60), except that a bounded level whose last column
 // is 60 q + 60 lets the last strip's lane 62 carry it (that column is a copy of
@@ -384,7 +393,7 @@ __host__ __device__ inline int strip_count(int nx, bool periodic)
     return (nx + STRIP - 1) / STRIP;
 }
 
-// element slot of column i within a plane row
+// slot index of column i (64 * strip + position in the strip)
 __device__ __forceinline__ unsigned col_slot(int i, int nstrip)
 {
     const int q = min(i / STRIP, nstrip - 1);
@@ -393,80 +402,77 @@ __device__ __forceinline__ unsigned col_slot(int i, int nstrip)
 
 struct StateFP64 {
     char *p;
-    int W, ny, nstrip; // W: elements per plane row (64 * nstrip)
-    unsigned pitch;    // bytes per row block
-    static constexpr unsigned PITCH_PER_SLOT = 160;
+    int ny, nstrip;
+    unsigned pitch; // bytes per row block
+    static constexpr unsigned BLOCK = 20u * SLOTS * 8u; // bytes per strip block (160 B per slot)
     __device__ static __forceinline__ StateFP64 make(void *b, int ny, int nstrip)
     {
-        return StateFP64{(char *)b, SLOTS * nstrip, ny, nstrip, PITCH_PER_SLOT * (unsigned)(SLOTS * nstrip)};
+        return StateFP64{(char *)b, ny, nstrip, BLOCK * (unsigned)nstrip};
     }
     __device__ static __forceinline__ unsigned esize(int, int) { return 8u; }
-    // byte offset of plane (v, s) within a row block of plane rows W elements wide
-    __device__ static __forceinline__ unsigned poff(int W, int v, int s) { return (unsigned)(v * 5 + s) * (unsigned)W * 8u; }
+    // byte offset of plane (v, s) within a strip block
+    __device__ static __forceinline__ unsigned poff(int v, int s) { return (unsigned)(s * 4 + v) * SLOTS * 8u; }
+    // byte offset of slot index `slot` within a row block, for the element size of plane (v, s)
+    __device__ static __forceinline__ unsigned lane_off(unsigned slot, int, int)
+    {
+        return (slot / SLOTS) * BLOCK + (slot % SLOTS) * 8u;
+    }
     // first byte of realization m
     __device__ __forceinline__ char *real_base(int m) const { return p + (size_t)m * (size_t)ny * pitch; }
     __device__ __forceinline__ size_t at(int v, int s, int m, int j, int i) const
     {
-        return ((size_t)m * (size_t)ny + (size_t)j) * pitch + poff(W, v, s) + (size_t)col_slot(i, nstrip) * 8u;
+        return ((size_t)m * (size_t)ny + (size_t)j) * pitch + lane_off(col_slot(i, nstrip), v, s) + poff(v, s);
     }
     __device__ __forceinline__ double ld(int v, int s, int m, int j, int i) const { return *(const double *)(p + at(v, s, m, j, i)); }
     __device__ __forceinline__ void st(int v, int s, int m, int j, int i, double x) const { *(double *)(p + at(v, s, m, j, i)) = x; }
     // value a store of x in variable v reads back as
     __device__ static __forceinline__ double stored(int, double x) { return x; }
-    __device__ static __forceinline__ double ldp(const char *base, int, int, unsigned off)
-    {
-        return *(const double *)(base + off);
-    }
-    // streaming store (the step kernel writes every line once, whole)
-    __device__ static __forceinline__ void stp(char *base, int, int, unsigned off, double x)
-    {
-        __builtin_nontemporal_store(x, (double *)(base + off));
-    }
     // Raw element bits for prefetching: the conversion to double happens at the
     // point of use, so a load in flight is not waited for at the loop back-edge.
-    __device__ static __forceinline__ unsigned long long ldraw(const char *base, int, int, unsigned off)
-    {
-        return *(const unsigned long long *)(base + off);
-    }
     __device__ static __forceinline__ double decode(int, int, unsigned long long r) { return __longlong_as_double((long long)r); }
-    // Buffer forms used by the step kernel: `rsrc` covers one row block, voff is
-    // the lane's byte offset within a plane row, soff the plane's offset.
-    __device__ static __forceinline__ unsigned long long ldbuf(__amdgpu_buffer_rsrc_t rsrc, int, int, unsigned voff,
-                                                               unsigned soff)
+    // Buffer forms used by the step kernel: `rsrc` covers one row block, lane_off
+    // is the lane's byte offset within it, plane_off the plane's offset within a
+    // strip block.
+    __device__ static __forceinline__ unsigned long long ldbuf(__amdgpu_buffer_rsrc_t rsrc, int, int, unsigned lane_off,
+                                                               unsigned plane_off)
     {
-        const u32x2 r = __builtin_amdgcn_raw_buffer_load_b64(rsrc, (int)voff, (int)soff, 0);
+        const u32x2 r = __builtin_amdgcn_raw_buffer_load_b64(rsrc, buf_voff(lane_off, plane_off), buf_soff(plane_off), 0);
         return ((unsigned long long)r.y << 32) | r.x;
     }
-    __device__ static __forceinline__ void stbuf(__amdgpu_buffer_rsrc_t rsrc, int, int, unsigned voff, unsigned soff,
-                                                 double x)
+    __device__ static __forceinline__ void stbuf(__amdgpu_buffer_rsrc_t rsrc, int, int, unsigned lane_off,
+                                                 unsigned plane_off, double x)
     {
         const unsigned long long b = (unsigned long long)__double_as_longlong(x);
         const u32x2 d = {(unsigned)(b & 0xffffffffull), (unsigned)(b >> 32)};
-        __builtin_amdgcn_raw_buffer_store_b64(d, rsrc, (int)voff, (int)soff, BUF_NT);
+        __builtin_amdgcn_raw_buffer_store_b64(d, rsrc, buf_voff(lane_off, plane_off), buf_soff(plane_off), BUF_NT);
     }
 };
 
 struct StateMixed {
     char *p;
-    int W, ny, nstrip;
+    int ny, nstrip;
     unsigned pitch;
-    static constexpr unsigned PITCH_PER_SLOT = 112;
+    static constexpr unsigned BLOCK = 8u * SLOTS * 8u + 12u * SLOTS * 4u; // 7168 B per strip block (112 B per slot)
     __device__ static __forceinline__ StateMixed make(void *b, int ny, int nstrip)
     {
-        return StateMixed{(char *)b, SLOTS * nstrip, ny, nstrip, PITCH_PER_SLOT * (unsigned)(SLOTS * nstrip)};
+        return StateMixed{(char *)b, ny, nstrip, BLOCK * (unsigned)nstrip};
     }
     __device__ static __forceinline__ bool is_f32(int v, int s) { return s > 0 && v < 3; }
     __device__ static __forceinline__ unsigned esize(int v, int s) { return is_f32(v, s) ? 4u : 8u; }
-    __device__ static __forceinline__ unsigned poff(int W, int v, int s)
+    __device__ static __forceinline__ unsigned poff(int v, int s)
     {
         if (is_f32(v, s))
-            return 64u * (unsigned)W + (unsigned)(v * 4 + (s - 1)) * (unsigned)W * 4u;
-        return (unsigned)(s == 0 ? v : 3 + s) * (unsigned)W * 8u;
+            return 8u * SLOTS * 8u + (unsigned)((s - 1) * 3 + v) * SLOTS * 4u;
+        return (unsigned)(s == 0 ? v : 3 + s) * SLOTS * 8u;
+    }
+    __device__ static __forceinline__ unsigned lane_off(unsigned slot, int v, int s)
+    {
+        return (slot / SLOTS) * BLOCK + (slot % SLOTS) * esize(v, s);
     }
     __device__ __forceinline__ char *real_base(int m) const { return p + (size_t)m * (size_t)ny * pitch; }
     __device__ __forceinline__ size_t at(int v, int s, int m, int j, int i) const
     {
-        return ((size_t)m * (size_t)ny + (size_t)j) * pitch + poff(W, v, s) + (size_t)col_slot(i, nstrip) * esize(v, s);
+        return ((size_t)m * (size_t)ny + (size_t)j) * pitch + lane_off(col_slot(i, nstrip), v, s) + poff(v, s);
     }
     __device__ __forceinline__ double ld(int v, int s, int m, int j, int i) const
     {
@@ -483,50 +489,32 @@ struct StateMixed {
     }
     // the macroscopic slot is FP64, so a stored u reads back unchanged
     __device__ static __forceinline__ double stored(int, double x) { return x; }
-    __device__ static __forceinline__ double ldp(const char *base, int v, int s, unsigned off)
-    {
-        if (is_f32(v, s))
-            return (double)*(const float *)(base + off);
-        return *(const double *)(base + off);
-    }
-    // streaming store (the step kernel writes every line once, whole)
-    __device__ static __forceinline__ void stp(char *base, int v, int s, unsigned off, double x)
-    {
-        if (is_f32(v, s))
-            __builtin_nontemporal_store((float)x, (float *)(base + off));
-        else
-            __builtin_nontemporal_store(x, (double *)(base + off));
-    }
-    __device__ static __forceinline__ unsigned long long ldraw(const char *base, int v, int s, unsigned off)
-    {
-        if (is_f32(v, s))
-            return (unsigned long long)*(const unsigned int *)(base + off);
-        return *(const unsigned long long *)(base + off);
-    }
     __device__ static __forceinline__ double decode(int v, int s, unsigned long long r)
     {
         if (is_f32(v, s))
             return (double)__uint_as_float((unsigned int)r);
         return __longlong_as_double((long long)r);
     }
-    __device__ static __forceinline__ unsigned long long ldbuf(__amdgpu_buffer_rsrc_t rsrc, int v, int s, unsigned voff,
-                                                               unsigned soff)
+    __device__ static __forceinline__ unsigned long long ldbuf(__amdgpu_buffer_rsrc_t rsrc, int v, int s, unsigned lane_off,
+                                                               unsigned plane_off)
     {
         if (is_f32(v, s))
-            return (unsigned long long)__builtin_amdgcn_raw_buffer_load_b32(rsrc, (int)voff, (int)soff, 0);
-        const u32x2 r = __builtin_amdgcn_raw_buffer_load_b64(rsrc, (int)voff, (int)soff, 0);
+            return (unsigned long long)__builtin_amdgcn_raw_buffer_load_b32(rsrc, buf_voff(lane_off, plane_off),
+                                                                            buf_soff(plane_off), 0);
+        const u32x2 r = __builtin_amdgcn_raw_buffer_load_b64(rsrc, buf_voff(lane_off, plane_off), buf_soff(plane_off), 0);
         return ((unsigned long long)r.y << 32) | r.x;
     }
-    __device__ static __forceinline__ void stbuf(__amdgpu_buffer_rsrc_t rsrc, int v, int s, unsigned voff, unsigned soff,
-                                                 double x)
+    __device__ static __forceinline__ void stbuf(__amdgpu_buffer_rsrc_t rsrc, int v, int s, unsigned lane_off,
+                                                 unsigned plane_off, double x)
     {
         if (is_f32(v, s)) {
-            __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint((float)x), rsrc, (int)voff, (int)soff, BUF_NT);
+            __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint((float)x), rsrc, buf_voff(lane_off, plane_off),
+                                                  buf_soff(plane_off), BUF_NT);
             return;
         }
         const unsigned long long b = (unsigned long long)__double_as_longlong(x);
         const u32x2 d = {(unsigned)(b & 0xffffffffull), (unsigned)(b >> 32)};
-        __builtin_amdgcn_raw_buffer_store_b64(d, rsrc, (int)voff, (int)soff, BUF_NT);
+        __builtin_amdgcn_raw_buffer_store_b64(d, rsrc, buf_voff(lane_off, plane_off), buf_soff(plane_off), BUF_NT);
     }
 };
 

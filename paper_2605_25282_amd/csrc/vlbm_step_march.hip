@@ -21,11 +21,12 @@
 // value of the state is read from memory once (plus the 2-column and 2-row
 // halos of the stencil; the halo lanes read a neighbouring strip only where
 // the stencil uses it) and written once, each store instruction covering the
-// strip's whole 64-slot block of a plane row (see the layout in
+// whole 64-element run of one plane in the strip's block (see the layout in
 // vlbm_device.h): 320 B per FP64 node update.  Loads and stores go through
-// raw buffer resources of one row block, so addresses are a scalar base and
-// plane offset plus one loop-invariant lane offset; stores and the limiter's
-// side conditions are lane-uniform or selects, so the loop has few branches.
+// raw buffer resources of one row block, so an address is a scalar base, one
+// loop-invariant lane offset and the plane's compile-time offset; stores and
+// the limiter's side conditions are lane-uniform or selects, so the loop has
+// few branches.
 //
 // Every arithmetic expression has the operand order of the reference form in
 // vlbm_kernels.hip (and of the oracle), so the result is bitwise identical.
@@ -122,7 +123,6 @@ __device__ __forceinline__ void march_item(const PhysArgs &ph, const LevelArgs &
     const char *const inb = Sin.real_base(m);
     char *const outb = Sout.real_base(m);
     const unsigned pitch = Sin.pitch;
-    const int W = Sin.W;
 
     // ---- geometry of this lane ----
     const int c = strip * STRIP - 2 + lane; // column
@@ -149,7 +149,7 @@ __device__ __forceinline__ void march_item(const PhysArgs &ph, const LevelArgs &
             return true;
         return kind_col_interior && j >= 1 && j <= ny - 2;
     };
-    // Lane offsets within a plane row.  Loads read the slot of the clamped (or
+    // Slot indices of this lane.  Loads read the slot of the clamped (or
     // wrapped) column cx.  Stores cover the strip's 64 slots with all lanes --
     // lane l writes slot (l - 2) mod 64, so lanes 2..61 (and lane 62 when it
     // carries the last column) land on their columns and the halo lanes fill
@@ -170,32 +170,53 @@ __device__ __forceinline__ void march_item(const PhysArgs &ph, const LevelArgs &
         const bool needed = !halo_lane || (q == 0 && lane == 1) || (q == 1 && lane == 62);
         slot_pop[q] = needed ? slot_in : slot_inner;
     }
-    auto col_in = [&](int v, int sl) -> unsigned { return (sl == 0 ? slot_in : slot_pop[sl - 1]) * St::esize(v, sl); };
+    // Byte offsets of the lane within a row block, in the two element sizes
+    // (v = 3 is an FP64 plane in every slot, v = 0 of a population slot the
+    // FP32 one of the mixed layout).
+    unsigned o_in = St::lane_off(slot_in, 3, 0), o_pop8[4], o_pop4[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        o_pop8[q] = St::lane_off(slot_pop[q], 3, 1 + q);
+        o_pop4[q] = St::lane_off(slot_pop[q], 0, 1 + q);
+    }
+    auto col_in = [&](int v, int sl) -> unsigned {
+        return sl == 0 ? o_in : (St::esize(v, sl) == 8u ? o_pop8[sl - 1] : o_pop4[sl - 1]);
+    };
     // The inlet column's lane stores its scheme values into the strip's last
     // (padding) slot, which the halo lanes fill with scratch values anyway; its
     // Dirichlet values go to its own slot.  So every scheme store is one store
     // by all lanes, with no branch on the lane.
     const unsigned slot_scheme = inlet_col ? (unsigned)(SLOTS * strip + SLOTS - 1) : slot_out;
-    auto col_out = [&](int v, int sl) -> unsigned { return slot_out * St::esize(v, sl); };
-    auto col_scheme = [&](int v, int sl) -> unsigned { return slot_scheme * St::esize(v, sl); };
+    auto col_out = [&](int v, int sl) -> unsigned { return St::lane_off(slot_out, v, sl); };
+    unsigned o_sch8 = St::lane_off(slot_scheme, 3, 1), o_sch4 = St::lane_off(slot_scheme, 0, 1);
+    auto col_scheme = [&](int v, int sl) -> unsigned { return St::esize(v, sl) == 8u ? o_sch8 : o_sch4; };
+    // The offsets are re-declared live in every iteration (an empty asm), so the
+    // constant plane offsets are added where the loads and stores are and fold
+    // into their immediate fields, instead of being hoisted into one register
+    // per plane.
+    auto pin_offsets = [&]() {
+        asm volatile("" : "+v"(o_in), "+v"(o_pop8[0]), "+v"(o_pop8[1]), "+v"(o_pop8[2]), "+v"(o_pop8[3]), "+v"(o_sch8));
+        if constexpr (PREC == 1)
+            asm volatile("" : "+v"(o_pop4[0]), "+v"(o_pop4[1]), "+v"(o_pop4[2]), "+v"(o_pop4[3]), "+v"(o_sch4));
+    };
     double wmax = 0.0;
     int bad = 0;
     // Every access goes through a buffer resource of one row block (uniform, in
-    // scalar registers): the lane's column offset is the vector offset, the
-    // plane's offset within the row block the scalar offset.
+    // scalar registers): the lane's byte offset within the row block is the
+    // vector offset, the plane's offset within a strip block a constant.
     auto out_row = [&](int j) { return row_rsrc(outb + (size_t)((unsigned)j * pitch), pitch); };
     auto in_row = [&](int j) { return row_rsrc(inb + (size_t)((unsigned)j * pitch), pitch); };
     auto store_slot = [&](int sl, int j, const double x[4]) {
         const __amdgpu_buffer_rsrc_t rj = out_row(j);
 #pragma unroll
         for (int v = 0; v < 4; ++v)
-            St::stbuf(rj, v, sl, col_scheme(v, sl), St::poff(W, v, sl), x[v]);
+            St::stbuf(rj, v, sl, col_scheme(v, sl), St::poff(v, sl), x[v]);
     };
     auto store_inlet = [&](int sl, int j, const double x[4]) {
         const __amdgpu_buffer_rsrc_t rj = out_row(j);
 #pragma unroll
         for (int v = 0; v < 4; ++v)
-            St::stbuf(rj, v, sl, col_out(v, sl), St::poff(W, v, sl), x[v]);
+            St::stbuf(rj, v, sl, col_out(v, sl), St::poff(v, sl), x[v]);
     };
     // wave-speed maximum and admissibility of a stored state, for the lanes in `mask`
     auto account = [&](const double u[4], bool mask) {
@@ -262,12 +283,12 @@ __device__ __forceinline__ void march_item(const PhysArgs &ph, const LevelArgs &
         const __amdgpu_buffer_rsrc_t ru = in_row(ju), rp = in_row(jp);
 #pragma unroll
         for (int v = 0; v < 4; ++v)
-            Ux[v] = St::decode(v, 0, St::ldbuf(ru, v, 0, col_in(v, 0), St::poff(W, v, 0)));
+            Ux[v] = St::decode(v, 0, St::ldbuf(ru, v, 0, col_in(v, 0), St::poff(v, 0)));
 #pragma unroll
         for (int q = 0; q < 4; ++q)
 #pragma unroll
             for (int v = 0; v < 4; ++v)
-                Px[q][v] = St::ldbuf(rp, v, 1 + q, col_in(v, 1 + q), St::poff(W, v, 1 + q));
+                Px[q][v] = St::ldbuf(rp, v, 1 + q, col_in(v, 1 + q), St::poff(v, 1 + q));
     };
     // an even number of iterations (a leading one on rows that are never stored
     // when chunk + 4 is odd), so the two buffers alternate without a join
@@ -276,6 +297,7 @@ __device__ __forceinline__ void march_item(const PhysArgs &ph, const LevelArgs &
     load_x(k_start + 1, UB, PB);
 
     auto iteration = [&](int k, double (&Ux)[4], unsigned long long (&Px)[4][4]) __attribute__((always_inline)) {
+        pin_offsets();
         double U0[4];
 #pragma unroll
         for (int v = 0; v < 4; ++v)
@@ -348,14 +370,25 @@ __device__ __forceinline__ void march_item(const PhysArgs &ph, const LevelArgs &
                                      side_main(P, LC, bC[0], bC[1], bC[2], Dyu),
                                      side_main(P, LB, bB[0], bB[1], bB[2], Dyd)};
             const bool use[4] = {inx1, inx2, iny1, iny2};
-            double th[4];
+            bool need[4];
+            double root[4];
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
-                double root = sd[i].th;
-                if (use[i] && sd[i].root)
-                    root = side_root(sd[i]);
-                th[i] = side_value(sd[i], root);
+                need[i] = use[i] && sd[i].root;
+                root[i] = sd[i].th;
             }
+            // one branch on all four (it depends on every side's main part, so
+            // none of them is deferred past another side's root)
+            if (need[0] || need[1] || need[2] || need[3]) {
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+                    if (need[i])
+                        root[i] = side_root(sd[i]);
+            }
+            double th[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+                th[i] = side_value(sd[i], root[i]);
             auto face = [&](bool in1, bool in2, double t1, double t2) {
                 double t = 1.0;
                 t = in1 ? fmin(t, t1) : t;
