@@ -31,7 +31,6 @@ grid on this host.
 from __future__ import annotations
 
 import argparse
-import hashlib
 import json
 import os
 import sys
@@ -42,22 +41,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "ensemble GLUPS (cell-updates/s summed over realizations) + % HBM roofline, FP64 vs mixed"
 HBM_PEAK_GBS = 8000.0
-# algorithmic bytes per node update: 20 values read + 20 written; the mixed
-# variant stores the populations' rho, rho v in FP32 (112 B per node)
-BYTES_PER_LUP = {"fp64": 320.0, "mixed": 224.0}
-
-
-STEP_KERNEL_SOURCES = ("vlbm_step_march.hip", "vlbm_device.h")
-
-
-def kernel_source_hash() -> str:
-    """Hash of the step kernel's sources: a committed traffic measurement is
-    reported only while the kernel it was taken on is unchanged."""
-    h = hashlib.sha256()
-    for f in STEP_KERNEL_SOURCES:
-        with open(os.path.join(ROOT, "paper_2605_25282_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
-    return h.hexdigest()[:16]
+from paper_2605_25282_amd.rocprof_summary import BYTES_PER_LUP, kernel_source_hash  # noqa: E402
 
 
 def measured_traffic(precision: str, workload: str, node_updates_per_launch: float | None = None):

@@ -2,6 +2,8 @@
 
     python -m paper_2605_25282_amd.rocprof_summary stats TRACE_kernel_stats.csv
     python -m paper_2605_25282_amd.rocprof_summary traffic FETCH_results.db WRITE_results.db KERNEL_SUBSTRING
+    python -m paper_2605_25282_amd.rocprof_summary record FETCH_results.db WRITE_results.db KERNEL_SUBSTRING \
+        PRECISION NODE_UPDATES_PER_LAUNCH WORKLOAD_TEXT SUMMARY_MD OUT.json
 
 `stats` prints the kernel-statistics table of a `rocprofv3 --kernel-trace --stats
 --output-format csv` run.  `traffic` reads the databases of two `rocprofv3 --pmc
@@ -9,17 +11,37 @@ FETCH_SIZE` / `--pmc WRITE_SIZE` runs of the same command, calibrates each
 counter by what it reads for the plain 2 GiB device copy the profiled command
 ends with (torch's copy kernel: 2 GiB read and 2 GiB written), and prints the
 HBM bytes per dispatch of the kernels whose name contains KERNEL_SUBSTRING
-(median over dispatches) as JSON.
+(median over dispatches) as JSON.  `record` writes the same figures as the
+traffic record the benchmark reads (with the algorithmic bytes of the given node
+updates per launch and the hash of the step kernel's current sources, so the
+record is ignored once the kernel changes).
 """
 from __future__ import annotations
 
 import csv
+import hashlib
 import json
+import os
 import sqlite3
 import statistics
 import sys
 
 COPY_BYTES = 1 << 31  # the calibration copy: 2^28 doubles
+CSRC = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc")
+STEP_KERNEL_SOURCES = ("vlbm_step_march.hip", "vlbm_device.h")
+# algorithmic bytes per node update: 20 values read + 20 written; the mixed
+# variant stores the populations' rho, rho v in FP32
+BYTES_PER_LUP = {"fp64": 320.0, "mixed": 224.0}
+
+
+def kernel_source_hash() -> str:
+    """Hash of the step kernel's sources: a committed traffic measurement is
+    reported only while the kernel it was taken on is unchanged."""
+    h = hashlib.sha256()
+    for f in STEP_KERNEL_SOURCES:
+        with open(os.path.join(CSRC, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
 
 
 def kernel_stats(path: str) -> list[dict]:
@@ -62,6 +84,19 @@ def traffic(fetch_db: str, write_db: str, kernel: str) -> dict:
     return res
 
 
+def record(fetch_db: str, write_db: str, kernel: str, precision: str, node_updates: float, workload: str,
+           source: str) -> dict:
+    """Traffic record of one workload: calibrated bytes per launch, the
+    algorithmic bytes of its node updates and the step kernel's source hash."""
+    t = traffic(fetch_db, write_db, kernel)
+    return {"bytes_per_launch": t["bytes_per_launch"],
+            "fetch_bytes": t["fetch"]["median_bytes"], "write_bytes": t["write"]["median_bytes"],
+            "node_updates_per_launch": node_updates,
+            "algorithmic_bytes_per_launch": BYTES_PER_LUP[precision] * node_updates,
+            "kernel": kernel, "workload": workload, "kernel_source_hash": kernel_source_hash(),
+            "source": source, "hashed_sources": list(STEP_KERNEL_SOURCES)}
+
+
 def main(argv: list[str]) -> int:
     if len(argv) >= 2 and argv[0] == "stats":
         print("| kernel | calls | total ms | avg us | % |\n|---|---|---|---|---|")
@@ -71,6 +106,13 @@ def main(argv: list[str]) -> int:
         return 0
     if len(argv) == 4 and argv[0] == "traffic":
         print(json.dumps(traffic(argv[1], argv[2], argv[3]), indent=1))
+        return 0
+    if len(argv) == 9 and argv[0] == "record":
+        rec = record(argv[1], argv[2], argv[3], argv[4], float(argv[5]), argv[6], argv[7])
+        with open(argv[8], "w") as f:
+            json.dump(rec, f, indent=1)
+            f.write("\n")
+        print(json.dumps(rec, indent=1))
         return 0
     print(__doc__)
     return 2

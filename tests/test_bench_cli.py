@@ -12,6 +12,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 sys.path.insert(0, ROOT)
 
 import bench  # noqa: E402
+from paper_2605_25282_amd import rocprof_summary  # noqa: E402
 
 
 def _run(*args):
@@ -42,7 +43,7 @@ def test_traffic_figure_is_tied_to_the_kernel_sources():
     for prec in ("fp64", "mixed"):
         path = os.path.join(ROOT, "profiles", f"traffic_step_c5_{prec}.json")
         rec = json.load(open(path))
-        assert rec["hashed_sources"] == list(bench.STEP_KERNEL_SOURCES)
+        assert rec["hashed_sources"] == list(rocprof_summary.STEP_KERNEL_SOURCES)
         got = bench.measured_traffic(prec, "c5")
         if rec["kernel_source_hash"] == bench.kernel_source_hash():
             assert got == rec["bytes_per_launch"]
@@ -64,3 +65,46 @@ def test_without_a_gpu_the_benchmark_fails_loudly():
     r = _run("--steps", "1", "--warmup", "0", "--no-cpu-baseline")
     assert r.returncode == 2
     assert json.loads(r.stdout.strip().splitlines()[-1])["error"] == "no GPU visible"
+
+
+def _counter_db(path, counter, rows):
+    """A rocprofv3-style counter database: (dispatch, kernel, value in KiB) per
+    dispatch, split over two counter instances as the profiler reports them."""
+    import sqlite3
+    c = sqlite3.connect(path)
+    c.execute("create table counters_collection (dispatch_id integer, kernel_name text, counter_name text, "
+              "value real)")
+    for d, k, v in rows:
+        c.execute("insert into counters_collection values (?, ?, ?, ?)", (d, k, counter, v * 0.25))
+        c.execute("insert into counters_collection values (?, ?, ?, ?)", (d, k, counter, v * 0.75))
+    c.commit()
+    c.close()
+
+
+def test_counter_summary_calibrates_by_the_last_copy(tmp_path):
+    """FETCH_SIZE / WRITE_SIZE are scaled by what they read for the 2 GiB
+    calibration copy at the end of the run (here: fetch reads half the copied
+    bytes, write all of them), the median over the kernel's dispatches is taken,
+    and the record carries the algorithmic bytes and the kernel's source hash."""
+    kib = (1 << 31) / 1024.0
+    fetch, write = tmp_path / "f.db", tmp_path / "w.db"
+    _counter_db(fetch, "FETCH_SIZE", [(1, "vlbm::step_march_kernel<0>", 100.0), (2, "vlbm::step_march_kernel<0>", 130.0),
+                                      (3, "vlbm::step_march_kernel<0>", 110.0), (4, "other", 5.0),
+                                      (5, "elementwise copy", kib / 2)])
+    _counter_db(write, "WRITE_SIZE", [(1, "vlbm::step_march_kernel<0>", 90.0), (2, "vlbm::step_march_kernel<0>", 90.0),
+                                      (3, "vlbm::step_march_kernel<0>", 95.0), (4, "copyBuffer", kib)])
+    t = rocprof_summary.traffic(str(fetch), str(write), "step_march_kernel")
+    assert t["fetch"]["scale"] == pytest.approx(2.0)
+    assert t["write"]["scale"] == pytest.approx(1.0)
+    assert t["fetch"]["median_bytes"] == pytest.approx(110.0 * 1024 * 2)
+    assert t["write"]["median_bytes"] == pytest.approx(90.0 * 1024)
+    assert t["bytes_per_launch"] == pytest.approx(110.0 * 2048 + 90.0 * 1024)
+    rec = rocprof_summary.record(str(fetch), str(write), "step_march_kernel", "mixed", 1000.0, "w", "s.md")
+    assert rec["algorithmic_bytes_per_launch"] == 224.0 * 1000
+    assert rec["kernel_source_hash"] == rocprof_summary.kernel_source_hash() == bench.kernel_source_hash()
+    assert rec["bytes_per_launch"] == pytest.approx(t["bytes_per_launch"])
+    # a run without a calibration copy is refused
+    bare = tmp_path / "b.db"
+    _counter_db(bare, "FETCH_SIZE", [(1, "vlbm::step_march_kernel<0>", 100.0)])
+    with pytest.raises(RuntimeError):
+        rocprof_summary.traffic(str(bare), str(write), "step_march_kernel")
