@@ -144,11 +144,11 @@ __device__ __forceinline__ void march_item(const PhysArgs &ph, const LevelArgs &
     const int y0 = chunk * ma.chunk, y1 = min(ny, y0 + ma.chunk);
 
     auto row_of = [&](int j) { return periodic ? ((j % ny) + ny) % ny : min(max(j, 0), ny - 1); };
-    auto interior = [&](int j) -> bool {
-        if (periodic)
-            return true;
-        return kind_col_interior && j >= 1 && j <= ny - 2;
-    };
+    // interior node: every node of a periodic level, else rows 1..ny-2 of an
+    // interior column (one unsigned compare on the row)
+    const bool col_int = periodic || kind_col_interior;
+    const unsigned int_rows = periodic ? 0xffffffffu : (unsigned)max(ny - 2, 0);
+    auto interior = [&](int j) -> bool { return col_int && (unsigned)(j - (periodic ? 0 : 1)) < int_rows; };
     // Slot indices of this lane.  Loads read the slot of the clamped (or
     // wrapped) column cx.  Stores cover the strip's 64 slots with all lanes --
     // lane l writes slot (l - 2) mod 64, so lanes 2..61 (and lane 62 when it
@@ -245,11 +245,14 @@ __device__ __forceinline__ void march_item(const PhysArgs &ph, const LevelArgs &
     // the adjacent interior row.  The stored values of the output lanes but the
     // inlet's (written on its own) enter the wave-speed maximum and the
     // admissibility check.
-    auto row_written = [&](int j) { return j >= y0 && j < y1 && (periodic || (j != 0 && j != ny - 1)); };
+    const int w_lo = periodic ? y0 : max(y0, 1), w_hi = periodic ? y1 : min(y1, ny - 1);
+    const unsigned w_span = (unsigned)max(w_hi - w_lo, 0);
+    auto row_written = [&](int j) { return (unsigned)(j - w_lo) < w_span; };
     const bool scheme_lane = out_lane && !inlet_col;
     // (a level with ny = 3 duplicates its single interior row into both)
-    auto dup_lo = [&](int j) { return !periodic && j == 1; };
-    auto dup_hi = [&](int j) { return !periodic && j == ny - 2; };
+    const int dup_lo_row = periodic ? -1 : 1, dup_hi_row = periodic ? -1 : ny - 2;
+    auto dup_lo = [&](int j) { return j == dup_lo_row; };
+    auto dup_hi = [&](int j) { return j == dup_hi_row; };
 
     // ---- register ring ----
     // Row k-2, finished in iteration k: (u1+u2)+u3, the correction without its
@@ -276,8 +279,10 @@ __device__ __forceinline__ void march_item(const PhysArgs &ph, const LevelArgs &
     const int k_first = y0 - 2, k_last = y1 + 1;
     // population row needed by iteration k is k-1; rows below y0-1 or above y1
     // never reach a stored value
-    auto prow = [&](int k) { return row_of(min(max(k - 1, y0 - 1), y1)); };
-    auto urow = [&](int k) { return row_of(min(k, k_last)); };
+    // (a bounded level clamps to [0, ny-1]; the bounds are folded once)
+    const int p_lo = max(y0 - 1, 0), p_hi = min(y1, ny - 1), u_hi = min(k_last, ny - 1);
+    auto prow = [&](int k) { return periodic ? row_of(min(max(k - 1, y0 - 1), y1)) : min(max(k - 1, p_lo), p_hi); };
+    auto urow = [&](int k) { return periodic ? row_of(min(k, k_last)) : min(max(k, 0), u_hi); };
     auto load_x = [&](int k, double (&Ux)[4], unsigned long long (&Px)[4][4]) {
         const int ju = urow(k), jp = prow(k);
         const __amdgpu_buffer_rsrc_t ru = in_row(ju), rp = in_row(jp);
