@@ -149,9 +149,9 @@ def main() -> int:
     ap.add_argument("--chunk-rows", type=int, default=0,
                     help="rows per wave of the step kernel (0: autotuned / default)")
     ap.add_argument("--decomposition", default="",
-                    help="with --no-tune, c5: the step kernel's whole decomposition as "
+                    help="with --no-tune: the step kernel's whole decomposition as "
                          "CHUNKS:WAVES_PER_BLOCK:ITEM_ORDER:DEALING, CHUNKS comma-separated per level "
-                         "(coarse, fine), e.g. 79,79:4:0:1 (a profiler run of a tuned configuration)")
+                         "(c5: coarse, fine), e.g. 79,79:4:0:1 (a profiler run of a tuned configuration)")
     ap.add_argument("--mixed-error", action="store_true",
                     help="instead of the default line: statistics of a mixed and of a one-ulp-"
                          "perturbed FP64 ensemble against an FP64 ensemble of the same seeds, at "
@@ -558,12 +558,19 @@ def run_pass(args, torch, vlbm, inputs) -> int:
                         (vlbm._VP * 2)(bufs[0].data_ptr(), bufs[1].data_ptr()))
         return lv, bufs
 
+    def fixed_tuning(h):
+        """--decomposition (whole) or --chunk-rows (item height) on handle h."""
+        if args.decomposition:
+            ch, wpb, order, deal = args.decomposition.split(":")
+            vlbm.vlbm_set_tuning(h, [int(c) for c in ch.split(",")], int(wpb), int(order), int(deal))
+        elif args.chunk_rows:
+            vlbm.vlbm_tune(h, "march", args.chunk_rows)
+
     if args.profile_launches > 0:
         params = vlbm.Params.jet(precision=args.precision if args.precision != "both" else "fp64")
         level, bufs = make_level(params)
         h = vlbm.vlbm_init_ensemble(params, [level], coefs, R, stream)
-        if args.chunk_rows:
-            vlbm.vlbm_tune(h, "march", args.chunk_rows)
+        fixed_tuning(h)
         vlbm.vlbm_step(h, w.t_final, args.profile_launches, want_done=True)
         vlbm.vlbm_destroy(h)
         a = torch.ones(1 << 28, dtype=torch.float64, device="cuda")
@@ -587,7 +594,7 @@ def run_pass(args, torch, vlbm, inputs) -> int:
         w1m = torch.zeros(1, dtype=torch.float64, device="cuda")
         # Autotune on live steps of a first ensemble (outside the timed region);
         # later ensembles of the same shape reuse the cached choice.
-        tuned = [args.chunk_rows]
+        tuned = [args.decomposition or args.chunk_rows]
         tune = tune and not args.no_tune
         if tune:
             h = vlbm.vlbm_init_ensemble(params, [level], coefs, R, stream)
@@ -607,8 +614,7 @@ def run_pass(args, torch, vlbm, inputs) -> int:
             # vlbm_step reads the completion flag back)
             c0 = time.perf_counter()
             h = vlbm.vlbm_init_ensemble(params, [level], coefs, R, stream)
-            if args.chunk_rows:
-                vlbm.vlbm_tune(h, "march", args.chunk_rows)
+            fixed_tuning(h)
             c1 = time.perf_counter()
             done = False
             while not done:
