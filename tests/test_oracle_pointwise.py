@@ -159,5 +159,20 @@ def test_side_theta_limits():
     th = O.side_theta(p, L, 0.5, 10.0, rhoeL, D)
     v = L + th * D
     assert v[3] - 0.5 * (v[1] ** 2 + v[2] ** 2) / v[0] == pytest.approx(p.pos_eps * rhoeL, rel=1e-12)
+    # energy-limited with the density changing too (the eps * rhoeL * rho(theta)
+    # term of the constraint moves with theta): density adds 0.2 per unit theta,
+    # momentum 2.0, energy -0.8; the returned theta puts the state on the floor
+    # rho e = eps * rhoeL and stays below the (loose) density limit
+    D = np.array([0.2, 2.0, 0.0, -0.8])
+    th = O.side_theta(p, L, 0.5, 10.0, rhoeL, D)
+    assert 0.0 < th < 1.0
+    v = L + th * D
+    assert v[3] - 0.5 * (v[1] ** 2 + v[2] ** 2) / v[0] == pytest.approx(p.pos_eps * rhoeL, rel=1e-12)
+    # a larger eps moves the floor, and theta with it
+    p2 = O.Params(pos_eps=0.3)
+    th2 = O.side_theta(p2, L, 0.5, 10.0, rhoeL, D)
+    v = L + th2 * D
+    assert th2 < th
+    assert v[3] - 0.5 * (v[1] ** 2 + v[2] ** 2) / v[0] == pytest.approx(0.3 * rhoeL, rel=1e-12)
     # non-positive low-order internal energy -> no antidiffusion
     assert O.side_theta(p, L, 0.5, 10.0, 0.0, D) == 0.0

@@ -229,6 +229,52 @@ def test_jet_local_bounds_and_energy_floor():
         st = new
 
 
+def test_relaxed_bounds_on_resting_states():
+    """Reading R3's relaxed local density bounds.  At rest the bar states
+    M_k(neighbour)/w carry exactly the neighbours' densities (the fluxes'
+    density components are the momenta, zero here), so with alpha > 0 a cell's
+    bar densities are its own and its four neighbours'.  Then: the bounds
+    contain every one of them; in a locally uniform region they collapse onto
+    the density (the relaxation scales with the local range, not with the
+    density); and next to a hundredfold jump the lower bound stays positive,
+    at least half the smallest bar density (a relaxation of 0.1 of the range
+    alone would go below zero there)."""
+    p = O.Params(bc="periodic", gamma=1.4)
+    g = O.Grid(16, 12, 1.0 / 16)
+    rho = np.ones((g.ny, g.nx))
+    rho[:, 8:] = 100.0
+    zero = np.zeros_like(rho)
+    u = _prim_to_cons(rho, zero, zero, np.ones_like(rho), p.gamma)
+    st = O.from_macroscopic(p, g, u)
+    _, rc, _, _, bd = O.step(p, g, O.kinetic_speed(p, g, st), st, diagnostics=True)
+    assert rc == O.OK
+    rmin, rmax = bd[0], bd[1]
+    nb = np.stack([rho, np.roll(rho, 1, 1), np.roll(rho, -1, 1), np.roll(rho, 1, 0), np.roll(rho, -1, 0)])
+    lo, hi = nb.min(axis=0), nb.max(axis=0)
+    assert np.all(rmin <= lo) and np.all(rmax >= hi)
+    flat = lo == hi
+    assert flat.sum() > 100 and np.array_equal(rmin[flat], rho[flat]) and np.array_equal(rmax[flat], rho[flat])
+    jump = ~flat
+    assert jump.sum() == 4 * g.ny
+    assert np.all(rmin[jump] > 0.0) and np.all(rmin[jump] >= 0.5 * lo[jump])
+    assert np.all(rmax[jump] > hi[jump])
+
+
+def test_low_order_internal_energy_of_a_uniform_flow():
+    """The low-order state of a uniform flow at equilibrium is the flow itself
+    (alpha u + the four Maxwellians sum to u), so its internal energy rho e is
+    p / (gamma - 1) of the flow: here 3.75, against a kinetic energy 10 times
+    larger."""
+    p = O.Params(bc="periodic", gamma=1.4)
+    g = O.Grid(10, 8, 0.1)
+    one = np.ones((g.ny, g.nx))
+    u = _prim_to_cons(2.0 * one, 6.0 * one, -2.0 * one, 1.5 * one, p.gamma)
+    st = O.from_macroscopic(p, g, u)
+    _, rc, _, _, bd = O.step(p, g, O.kinetic_speed(p, g, st), st, diagnostics=True)
+    assert rc == O.OK
+    np.testing.assert_allclose(bd[2], 1.5 / (p.gamma - 1.0), rtol=1e-12)
+
+
 def test_jet_run_admissible_and_lands_on_t_final():
     """A full 128 x 64 realization to t = 1e-4: admissible throughout, t_final hit exactly,
     the inlet column untouched (Dirichlet, eq:inletBC) and the step count consistent
