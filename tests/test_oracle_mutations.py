@@ -1,0 +1,182 @@
+"""How well the pins hold the oracle: each case plants one plausible slip in a
+scratch copy of the oracle (a sign, a factor, a neighbour, an index, a
+normalisation, a skipped term), runs the CPU oracle tests against that copy
+in a child process and requires at least one of them to fail.  The real
+oracle is never modified; the slips live only in temporary files."""
+import concurrent.futures as cf
+import os
+import shutil
+import subprocess
+import sys
+import tempfile
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+C_SRC = os.path.join(ROOT, "oracle", "vlbm_oracle.c")
+PY_SRC = os.path.join(ROOT, "oracle", "__init__.py")
+PIN_TESTS = sorted(f for f in os.listdir(os.path.join(ROOT, "tests"))
+                   if f.startswith("test_oracle_") and f not in ("test_oracle_sanitized.py", "test_oracle_mutations.py"))
+WORKERS = max(1, min(8, os.cpu_count() or 1))
+
+# (what the slip is, text of the oracle, text it is replaced with)
+C_SLIPS = [
+    ("pressure: sign inside |v|^2", "    const double p = (P->gamma - 1.0) * (E - 0.5 * rho * (v1 * v1 + v2 * v2));\n    f[0] = m1;",
+     "    const double p = (P->gamma - 1.0) * (E - 0.5 * rho * (v1 * v1 - v2 * v2));\n    f[0] = m1;"),
+    ("flux f_2 minus p", "f[1] = m1 * v1 + p;", "f[1] = m1 * v1 - p;"),
+    ("flux g_3 without p", "g[2] = m2 * v2 + p;", "g[2] = m2 * v2;"),
+    ("flux f_4 without p", "f[3] = (E + p) * v1;", "f[3] = E * v1;"),
+    ("flux g_2 with v2", "g[1] = m2 * v1;", "g[1] = m2 * v2;"),
+    ("M_2 with + f", "M[1 * 4 + v] = wu - h * f[v];", "M[1 * 4 + v] = wu + h * f[v];"),
+    ("M_3 with f", "M[2 * 4 + v] = wu + h * g[v];", "M[2 * 4 + v] = wu + h * f[v];"),
+    ("Maxwellian 1/a", "const double h = 1.0 / (2.0 * a);", "const double h = 1.0 / a;"),
+    ("weight (1-alpha)/5", "    const double w = (1.0 - P->alpha) / 4.0;\n    const double h",
+     "    const double w = (1.0 - P->alpha) / 5.0;\n    const double h"),
+    ("wave speed |v1|+|v2|", "return fmax(fabs(v1), fabs(v2)) + c;", "return fabs(v1) + fabs(v2) + c;"),
+    ("sound speed without gamma", "const double c = sqrt(P->gamma * p / rho);", "const double c = sqrt(p / rho);"),
+    ("kinetic speed without 2", "return P->kappa * 2.0 * smax / (1.0 - P->alpha);", "return P->kappa * smax / (1.0 - P->alpha);"),
+    ("kinetic speed without 1-alpha", "return P->kappa * 2.0 * smax / (1.0 - P->alpha);", "return P->kappa * 2.0 * smax;"),
+    ("N = u - M", "= Mn[k * 4 + v] - ST(st, 1 + k, v, j, i);", "= ST(st, 1 + k, v, j, i) - Mn[k * 4 + v];"),
+    ("low-order state without alpha u", "L[v] = alpha * ST(st, 0, v, j, i) + M1[v] + M2[v] + M3[v] + M4[v];",
+     "L[v] = M1[v] + M2[v] + M3[v] + M4[v];"),
+    ("low-order M_2 from the west", "const double *M2 = M + NODE(ip, j) * 16 + 1 * 4;", "const double *M2 = M + NODE(im, j) * 16 + 1 * 4;"),
+    ("low-order M_4 from slot 3", "const double *M4 = M + NODE(i, jp) * 16 + 3 * 4;", "const double *M4 = M + NODE(i, jp) * 16 + 2 * 4;"),
+    ("bounds without own density", "                rmax = fmax(rmax, ST(st, 0, 0, j, i));\n", ""),
+    ("relaxation on rho_max", "const double delta = P->rlmp_relax * (rmax - rmin);", "const double delta = P->rlmp_relax * rmax;"),
+    ("no half-minimum floor", "RMIN[NODE(i, j)] = fmax(rmin - delta, 0.5 * rmin);", "RMIN[NODE(i, j)] = rmin - delta;"),
+    ("low-order rho e without 1/2", "RHOEL[NODE(i, j)] = L[3] - 0.5 * (L[1] * L[1] + L[2] * L[2]) / L[0];",
+     "RHOEL[NODE(i, j)] = L[3] - (L[1] * L[1] + L[2] * L[2]) / L[0];"),
+    ("side limiter rho_min for rho_max", "th = (rmax - L[0]) / D[0];", "th = (rmin - L[0]) / D[0];"),
+    ("energy quadratic: eps term sign", "- eps * rhoeL * D[0];", "+ eps * rhoeL * D[0];"),
+    ("energy quadratic: c0 without 1-eps", "const double c0 = (1.0 - eps) * L[0] * rhoeL;", "const double c0 = L[0] * rhoeL;"),
+    ("energy root sign", "r = 2.0 * c0 / (sq - c1);", "r = 2.0 * c0 / (sq + c1);"),
+    ("energy root never taken", "    if (q >= 0.0)\n        return th;", "    if (q >= -1e300)\n        return th;"),
+    ("x-face flux N_1 + N_2", "A[v] = N[NODE(i, j) * 16 + 0 * 4 + v] - N[NODE(i2, j) * 16 + 1 * 4 + v];",
+     "A[v] = N[NODE(i, j) * 16 + 0 * 4 + v] + N[NODE(i2, j) * 16 + 1 * 4 + v];"),
+    ("y-face flux N_3 - N_3", "A[v] = N[NODE(i, j) * 16 + 2 * 4 + v] - N[NODE(i, j2) * 16 + 3 * 4 + v];",
+     "A[v] = N[NODE(i, j) * 16 + 2 * 4 + v] - N[NODE(i, j2) * 16 + 2 * 4 + v];"),
+    ("x-face: one side only", "                        if (in2)\n                            th = fmin(th, orc_side_theta(P, UL + NODE(i2, j) * 4, RMIN[NODE(i2, j)],",
+     "                        if (0)\n                            th = fmin(th, orc_side_theta(P, UL + NODE(i2, j) * 4, RMIN[NODE(i2, j)],"),
+    ("u_1 with the east theta", "const double u1 = Mw[0 * 4 + v] + txm * Nw[0 * 4 + v];", "const double u1 = Mw[0 * 4 + v] + txp * Nw[0 * 4 + v];"),
+    ("u_4 from the south", "const double u4 = Mn[3 * 4 + v] + typ * Nn[3 * 4 + v];", "const double u4 = Ms[3 * 4 + v] + typ * Ns[3 * 4 + v];"),
+    ("correction sign", "- txm * Nc[1 * 4 + v] - txp * Nc[0 * 4 + v] -", "+ txm * Nc[1 * 4 + v] - txp * Nc[0 * 4 + v] -"),
+    ("correction N_1 and N_2 swapped", "- txm * Nc[1 * 4 + v] - txp * Nc[0 * 4 + v] -", "- txm * Nc[0 * 4 + v] - txp * Nc[1 * 4 + v] -"),
+    ("correction without alpha u", "const double corr = alpha * ST(st, 0, v, j, i) - txm", "const double corr = 0.0 - txm"),
+    ("inlet Maxwellians at 1.01 a", "                orc_maxwellians(P, a, u, Mi);", "                orc_maxwellians(P, 1.01 * a, u, Mi);"),
+    ("inlet keeps old populations", "                        ST(st_new, 1 + k, v, j, i) = Mi[k * 4 + v];",
+     "                        ST(st_new, 1 + k, v, j, i) = ST(st, 1 + k, v, j, i);"),
+    ("copy layers from the old state", "ST(st_new, s, v, j, i) = ST(st_new, s, v, js, is);", "ST(st_new, s, v, j, i) = ST(st, s, v, js, is);"),
+    ("copy layers one column short", "const int is = clampi(i, 1, nx - 2), js = clampi(j, 1, ny - 2);",
+     "const int is = clampi(i, 2, nx - 3), js = clampi(j, 1, ny - 2);"),
+    ("mixed storage rounds E", "        for (int v = 0; v < 3; ++v)\n            for (int j = 0; j < G->ny; ++j)",
+     "        for (int v = 0; v < 4; ++v)\n            for (int j = 0; j < G->ny; ++j)"),
+    ("mixed storage rounds u", "    for (int s = 1; s <= 4; ++s)\n        for (int v = 0; v < 3; ++v)",
+     "    for (int s = 0; s <= 4; ++s)\n        for (int v = 0; v < 3; ++v)"),
+    ("no halved second-last step", "        } else if (*t + 2.0 * dt > t_final) {", "        } else if (0) {"),
+    ("dt = dx / (2 a)", "double dt = G->dx / a;", "double dt = 0.5 * G->dx / a;"),
+    ("KL decay k^-1", "        for (int q = 0; q < P->kl_decay; ++q)\n            kp *= (double)k;",
+     "        for (int q = 0; q < 1; ++q)\n            kp *= (double)k;"),
+    ("KL cos and sin swapped", "s += amp * (Yk * cr_cos(k * M_PI * yb) + Zk * cr_sin(k * M_PI * yb));",
+     "s += amp * (Yk * cr_sin(k * M_PI * yb) + Zk * cr_cos(k * M_PI * yb));"),
+    ("window not squared", "    W = W * W;\n", ""),
+    ("window cos(pi y)", "double W = cr_cos(0.5 * M_PI * yb);", "double W = cr_cos(M_PI * yb);"),
+    ("inlet E without kinetic energy", "u[3] = P->p_amb / (P->gamma - 1.0) + 0.5 * rho * (v1 * v1);", "u[3] = P->p_amb / (P->gamma - 1.0);"),
+    ("jet velocity everywhere", "const double v1 = (fabs(y) <= P->r_jet) ? P->v_jet : 0.0;", "const double v1 = P->v_jet;"),
+    ("ambient density p_amb", "    u[0] = P->rho_amb;\n    u[1] = 0.0;", "    u[0] = P->p_amb;\n    u[1] = 0.0;"),
+    ("initial speed 1.1 a_0", "    const double a0 = orc_kinetic_speed(P, G, st);", "    const double a0 = 1.1 * orc_kinetic_speed(P, G, st);"),
+    ("admissibility rho e without 1/rho", "const double rhoe = E - 0.5 * (m1 * m1 + m2 * m2) / rho;",
+     "const double rhoe = E - 0.5 * (m1 * m1 + m2 * m2);"),
+]
+
+PY_SLIPS = [
+    ("speed |v1|+|v2|", "speed = np.sqrt(v1 * v1 + v2 * v2)", "speed = np.abs(v1) + np.abs(v2)"),
+    ("moment pressure without 1/2", "    pr = (p.gamma - 1.0) * (E - 0.5 * rho * (v1 * v1 + v2 * v2))\n    speed",
+     "    pr = (p.gamma - 1.0) * (E - 1.0 * rho * (v1 * v1 + v2 * v2))\n    speed"),
+    ("restriction / r", "return blocks.sum(axis=(-3, -1)) / (r * r)", "return blocks.sum(axis=(-3, -1)) / r"),
+    ("restriction blocks misaligned", "blocks = field.reshape(*lead, ny // r, r, nx // r, r)", "blocks = field.reshape(*lead, r, ny // r, r, nx // r)"),
+    ("sample std", "return np.sqrt(((samples - mean) ** 2).sum(axis=0) / samples.shape[0])",
+     "return np.sqrt(((samples - mean) ** 2).sum(axis=0) / (samples.shape[0] - 1))"),
+    ("variance for std", "return np.sqrt(((samples - mean) ** 2).sum(axis=0) / samples.shape[0])",
+     "return ((samples - mean) ** 2).sum(axis=0) / samples.shape[0]"),
+    ("W1 sorts one side", "return np.abs(np.sort(a, axis=0) - np.sort(b, axis=0)).sum(axis=0) / a.shape[0]",
+     "return np.abs(np.sort(a, axis=0) - b).sum(axis=0) / a.shape[0]"),
+    ("W1 over M-1", "return np.abs(np.sort(a, axis=0) - np.sort(b, axis=0)).sum(axis=0) / a.shape[0]",
+     "return np.abs(np.sort(a, axis=0) - np.sort(b, axis=0)).sum(axis=0) / (a.shape[0] - 1)"),
+    ("W1 opposite orders", "return np.abs(np.sort(a, axis=0) - np.sort(b, axis=0)).sum(axis=0) / a.shape[0]",
+     "return np.abs(np.sort(a, axis=0) - np.sort(b, axis=0)[::-1]).sum(axis=0) / a.shape[0]"),
+    ("E_strong relative to the coarse", "den = np.abs(fine_r[m]).sum()", "den = np.abs(coarse[m]).sum()"),
+    ("E_strong not averaged", "    return total / M\n", "    return total\n"),
+    ("cell mean of the signed difference", "return float(np.abs(x - y).sum() / x.size)", "return float(np.abs((x - y).sum()) / x.size)"),
+    ("quantile counts strictly below", 'count = np.searchsorted(s, s, side="right")', 'count = np.searchsorted(s, s, side="left")'),
+    ("quantile with >", "j = int(np.argmax(100 * count >= pct * M))", "j = int(np.argmax(100 * count > pct * M))"),
+    ("width ratio quantiles swapped",
+     "return (empirical_quantile(samples, 95) - empirical_quantile(samples, 5)) / \\\n        (empirical_quantile(samples, 84) - empirical_quantile(samples, 16))",
+     "return (empirical_quantile(samples, 95) - empirical_quantile(samples, 16)) / \\\n        (empirical_quantile(samples, 84) - empirical_quantile(samples, 5))"),
+    ("rate fit normalised by y", "r = float(((x - xm) * (y - ym)).sum() / ((x - xm) ** 2).sum())",
+     "r = float(((x - xm) * (y - ym)).sum() / ((y - ym) ** 2).sum())"),
+    ("Cauchy error at the finer width", "return [(l - 1, l, l - 1) for l in range(1, L + 1)]", "return [(l - 1, l, l) for l in range(1, L + 1)]"),
+    ("reference pairs include L", "return [(l, L, l) for l in range(L)]", "return [(l, L, l) for l in range(L + 1)]"),
+    ("subsample at interval starts", "return (2 * k + 1) * n // (2 * n_pd)", "return k * n // n_pd"),
+    ("2-D ground cost squared",
+     "cost = np.sqrt((p[:, None, 0] - q[None, :, 0]) ** 2 + (p[:, None, 1] - q[None, :, 1]) ** 2)",
+     "cost = (p[:, None, 0] - q[None, :, 0]) ** 2 + (p[:, None, 1] - q[None, :, 1]) ** 2"),
+    ("2-D ground cost L1",
+     "cost = np.sqrt((p[:, None, 0] - q[None, :, 0]) ** 2 + (p[:, None, 1] - q[None, :, 1]) ** 2)",
+     "cost = np.abs(p[:, None, 0] - q[None, :, 0]) + np.abs(p[:, None, 1] - q[None, :, 1])"),
+    ("W_{1,2} unordered pairs", "        for (j2, i2) in cells:\n            p = np.stack",
+     "        for (j2, i2) in cells[cells.index((j1, i1)):]:\n            p = np.stack"),
+    ("W_{1,2} second law's points swapped", "q = np.stack([b[:, j1, i1], b[:, j2, i2]], axis=1)",
+     "q = np.stack([b[:, j2, i2], b[:, j1, i1]], axis=1)"),
+]
+
+
+def _pytest(cwd, env):
+    r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-m", "not gpu", "-p", "no:cacheprovider",
+                        *[os.path.join("tests", t) for t in PIN_TESTS]], cwd=cwd, env=env, capture_output=True,
+                       text=True, timeout=1500)
+    return r.returncode, (r.stdout.strip().splitlines() or [""])[-1]
+
+
+def _c_case(slip):
+    name, old, new = slip
+    src = open(C_SRC).read()
+    assert src.count(old) == 1, f"{name}: the oracle text it changes is not unique"
+    with tempfile.TemporaryDirectory() as d:
+        c, lib = os.path.join(d, "m.c"), os.path.join(d, "libm.so")
+        open(c, "w").write(src.replace(old, new))
+        subprocess.run(["gcc", "-O2", "-std=gnu99", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared", c,
+                        "-o", lib, "-lquadmath", "-lm"], check=True, capture_output=True)
+        rc, last = _pytest(ROOT, dict(os.environ, ORACLE_LIB=lib))
+    return name, rc, last
+
+
+def _py_case(slip):
+    name, old, new = slip
+    src = open(PY_SRC).read()
+    assert src.count(old) == 1, f"{name}: the oracle text it changes is not unique"
+    with tempfile.TemporaryDirectory() as d:
+        tree = os.path.join(d, "tree")
+        os.makedirs(tree)
+        for sub in ("tests", "oracle", "paper_2605_25282_amd"):
+            shutil.copytree(os.path.join(ROOT, sub), os.path.join(tree, sub),
+                            ignore=shutil.ignore_patterns("__pycache__", "*.so", "csrc"))
+        open(os.path.join(tree, "oracle", "__init__.py"), "w").write(src.replace(old, new))
+        rc, last = _pytest(tree, dict(os.environ, ORACLE_LIB=os.path.join(ROOT, "oracle", "libvlbm_oracle.so")))
+    return name, rc, last
+
+
+@pytest.fixture(scope="module")
+def built_oracle():
+    if shutil.which("gcc") is None:
+        pytest.skip("gcc is not available")
+    import oracle
+    oracle.build(force=False)
+
+
+@pytest.mark.parametrize("kind", ["scheme (C)", "statistics (Python)"])
+def test_every_planted_slip_fails_a_pin(kind, built_oracle):
+    cases, fn = (C_SLIPS, _c_case) if kind.startswith("scheme") else (PY_SLIPS, _py_case)
+    with cf.ThreadPoolExecutor(max_workers=WORKERS) as ex:
+        results = list(ex.map(fn, cases))
+    survivors = [f"{name} ({last})" for name, rc, last in results if rc == 0]
+    assert not survivors, "slips no pin catches: " + "; ".join(survivors)
