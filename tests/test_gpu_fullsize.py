@@ -113,6 +113,28 @@ def test_largest_level_two_realizations():
         assert _plane_err(got[m], ref[m]) <= TOL, m
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_headline_pair_against_the_oracle(precision):
+    """The benchmark's launch: the 5056x2528 level and its 2528x1264 partner on
+    the same seeds, both advanced by one launch per step (graph replays), in
+    either storage; 2 realizations, 4 steps, every plane of both levels against
+    the oracle in the same storage (the mixed path rounds the same planes to
+    binary32 at the same points, so it is bitwise too)."""
+    fine = inputs.WORKLOADS["jet5056"]
+    works = [(fine.nx // 2, fine.ny // 2), (fine.nx, fine.ny)]
+    levels = [(nx, ny, 1.0 / nx, -0.25) for nx, ny in works]
+    R, steps = 2, 4
+    coefs = inputs.kl_coefficients(inputs.DEFAULT_SEED, 0, R)
+    ens = vlbm.Ensemble(vlbm.Params.jet(precision=precision), levels, coefs, R)
+    ens.step(1e30, steps)
+    got = [_picked(ens, l, (0, 1)) for l in range(2)]
+    ens.close()
+    for l, (nx, ny, dx, y_min) in enumerate(levels):
+        ref = _oracle(O.Params(storage=precision), O.Grid(nx, ny, dx, y_min), coefs, steps, (0, 1))
+        for m in (0, 1):
+            assert _plane_err(got[l][m], ref[m]) <= TOL, (precision, l, m)
+
+
 def test_headline_pair_is_independent_of_the_decomposition():
     """The benchmark's 5056x2528 + 2528x1264 pair (8 realizations here), 30
     steps of one launch per step under the work-queue dealing with the default
