@@ -135,6 +135,42 @@ def test_headline_pair_against_the_oracle(precision):
             assert _plane_err(got[l][m], ref[m]) <= TOL, (precision, l, m)
 
 
+@pytest.mark.parametrize("precision,decomposition", [("fp64", ([33, 32], 4, 0, 1)),
+                                                      ("mixed", ([64, 64], 4, 0, 1))])
+def test_headline_batch_sampled_against_the_oracle(precision, decomposition):
+    """The benchmark's whole launch: a batch of 45 realizations of the
+    5056x2528 + 2528x1264 pair (about 250 GB of state in FP64) at the
+    decomposition the default line tuned to, 4 steps; the density, speed and
+    pressure of realizations 0, 22 and 44 (the last one beyond 96 GB into the
+    fine level's buffer) of both levels equal the oracle's bit for bit."""
+    fine = inputs.WORKLOADS["jet5056"]
+    works = [(fine.nx // 2, fine.ny // 2), (fine.nx, fine.ny)]
+    levels = [(nx, ny, 1.0 / nx, -0.25) for nx, ny in works]
+    R, steps, picks = 45, 4, (0, 22, 44)
+    coefs = inputs.kl_coefficients(inputs.DEFAULT_SEED, 0, R)
+    torch.cuda.empty_cache()  # the batch takes most of HBM: start from an empty cache
+    ens = vlbm.Ensemble(vlbm.Params.jet(precision=precision), levels, coefs, R)
+    ens.set_tuning(*decomposition)
+    ens.step(1e30, steps)
+    got = []
+    for l in range(2):
+        t, s, a, status = ens.times(l)
+        assert np.all(s == steps) and np.all(status == 0)
+        mom = ens.moments(l)
+        got.append({m: [f[m].cpu().numpy() for f in mom] for m in picks})
+        del mom
+    ens.close()
+    del ens
+    torch.cuda.empty_cache()
+    p = O.Params(storage=precision)
+    for l, (nx, ny, dx, y_min) in enumerate(levels):
+        ref = _oracle(p, O.Grid(nx, ny, dx, y_min), coefs, steps, picks)
+        for m in picks:
+            want = O.moments(p, ref[m][0:4])
+            for f in range(3):
+                assert np.array_equal(got[l][m][f], want[f]), (precision, l, m, f)
+
+
 def test_headline_pair_is_independent_of_the_decomposition():
     """The benchmark's 5056x2528 + 2528x1264 pair (8 realizations here), 30
     steps of one launch per step under the work-queue dealing with the default
