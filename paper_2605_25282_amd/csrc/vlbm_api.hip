@@ -78,9 +78,6 @@ vlbm_status fail(vlbm_status code, const char *fmt, ...)
             return fail(VLBM_ERR_HIP, "%s launch failed: %s", what, hipGetErrorString(e_)); \
     } while (0)
 
-// Bytes of one state buffer: R x ny row blocks of 20 plane rows, each plane row
-// 64 element slots per column strip (FP64: 160 B per slot; mixed: 8 FP64 and
-// 12 FP32 planes, 112 B per slot).
 // Bytes of the per-ensemble control block: the three-launch ring of time, kinetic
 // speed, step count and wave-speed maximum, the status words, and the nine
 // counters of the dynamic work dealing.
@@ -90,6 +87,9 @@ size_t ctl_block_bytes(int nr)
            (size_t)nr * sizeof(int) + 9 * sizeof(unsigned);
 }
 
+// Bytes of one state buffer: R x ny row blocks, each of nstrip strip blocks
+// that hold 64 element positions of all 20 planes (FP64: 160 B per position;
+// mixed: 8 FP64 and 12 FP32 planes, 112 B per position).
 size_t state_bytes(int prec, int bc, int nx, int ny, int R)
 {
     const size_t slots = (size_t)SLOTS * (size_t)strip_count(nx, bc == VLBM_BC_PERIODIC);
