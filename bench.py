@@ -131,18 +131,18 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--precision", default="both", choices=["both", "fp64", "mixed"])
-    ap.add_argument("--workload", default="c5",
-                    help="c5 (default): the 5056x2528 level and its 2528x1264 partner, M = 1000 "
+    ap.add_argument("--workload", default="jet5056pair",
+                    help="jet5056pair (default): the 5056x2528 level and its 2528x1264 partner, M = 1000 "
                          "streamed in batches; or the name of a single-level jet workload "
                          "(jet128, jet320, jet640, jet1280), one step = one whole pass to t_final")
     ap.add_argument("--launches", type=int, default=60,
-                    help="c5: step launches per benchmark step")
+                    help="jet5056pair: step launches per benchmark step")
     ap.add_argument("--batch", type=int, default=0,
-                    help="c5: realizations per batch (0: the largest that fits in HBM, at most 64)")
+                    help="jet5056pair: realizations per batch (0: the largest that fits in HBM, at most 64)")
     ap.add_argument("--chunk", type=int, default=240, help="launches per vlbm_step call (whole passes)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed-error", action="store_true",
-                    help="c5: skip the mixed-vs-FP64 statistics comparison")
+                    help="jet5056pair: skip the mixed-vs-FP64 statistics comparison")
     ap.add_argument("--no-tune", action="store_true",
                     help="skip the autotuning pass (with --chunk-rows: a fixed step-kernel "
                          "configuration, e.g. for a profiler run of this same command)")
@@ -151,7 +151,7 @@ def main() -> int:
     ap.add_argument("--decomposition", default="",
                     help="with --no-tune: the step kernel's whole decomposition as "
                          "CHUNKS:WAVES_PER_BLOCK:ITEM_ORDER:DEALING, CHUNKS comma-separated per level "
-                         "(c5: coarse, fine), e.g. 79,79:4:0:1 (a profiler run of a tuned configuration)")
+                         "(jet5056pair: coarse, fine), e.g. 79,79:4:0:1 (a profiler run of a tuned configuration)")
     ap.add_argument("--mixed-error", action="store_true",
                     help="instead of the default line: statistics of a mixed and of a one-ulp-"
                          "perturbed FP64 ensemble against an FP64 ensemble of the same seeds, at "
@@ -166,12 +166,12 @@ def main() -> int:
     ap.add_argument("--study-m", type=int, default=0, help="realizations (0: 128 config, 32 paper)")
     ap.add_argument("--study-levels", type=int, default=3, choices=[3, 4],
                     help="paper geometry: 4 adds the 4000x3200 level (the paper's full hierarchy)")
-    ap.add_argument("--c5-full", action="store_true",
+    ap.add_argument("--pair-full", action="store_true",
                     help="instead of the default line: the largest level (5056x2528) with its "
                          "2528x1264 partner on the same seeds, whole batches streamed to t=1e-3 with "
                          "running mean/std and sample stores, then the one-point W1 between the levels")
-    ap.add_argument("--c5-batches", type=int, default=1)
-    ap.add_argument("--c5-batch-m", type=int, default=45)
+    ap.add_argument("--pair-batches", type=int, default=1)
+    ap.add_argument("--pair-batch-m", type=int, default=45)
     ap.add_argument("--w12", action="store_true",
                     help="instead of the default line: time the two-point W_{1,2} at the paper's "
                          "scale (1000 samples, 10 x 10 subsampled cells, 10^4 exact assignments) on "
@@ -183,7 +183,7 @@ def main() -> int:
                          "of the bands, shear-layer onset, leading fringe)")
     ap.add_argument("--profile-launches", type=int, default=0,
                     help="profiling mode: initial datum and this many step launches of the "
-                         "workload (c5: one batch, both levels), no statistics and no JSON line")
+                         "workload (jet5056pair: one batch, both levels), no statistics and no JSON line")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; multi-GPU runs are not "
@@ -200,18 +200,18 @@ def main() -> int:
     vlbm.lib()  # fails loudly if the HIP library was not built
     if args.study:
         return run_study(args, torch, vlbm, inputs)
-    if args.c5_full:
-        return run_c5(args, torch, vlbm, inputs)
+    if args.pair_full:
+        return run_pair_full(args, torch, vlbm, inputs)
     if args.w12:
         return run_w12(args, torch, vlbm)
     if args.centerline:
         return run_centerline(args, torch, vlbm, inputs)
     if args.mixed_error:
-        w = inputs.WORKLOADS["jet640" if args.workload == "c5" else args.workload]
+        w = inputs.WORKLOADS["jet640" if args.workload == "jet5056pair" else args.workload]
         out = mixed_error_study(torch, vlbm, inputs, w, (0.01, 0.1, 1.0), args.chunk)
         print(json.dumps({"mixed_error_study": out}), flush=True)
         return 0
-    if args.workload == "c5":
+    if args.workload == "jet5056pair":
         return run_headline(args, torch, vlbm, inputs)
     return run_pass(args, torch, vlbm, inputs)
 
@@ -318,11 +318,11 @@ def mixed_error_study(torch, vlbm, inputs, w, fracs, chunk):
     return {"workload": f"{w.name}: {w.nx}x{w.ny}, M={R}, same seeds", "rows": out}
 
 
-C5_M_TOTAL = 1000          # realizations of the whole job
-C5_HEADROOM = 6 << 30      # device bytes left free next to the batch
+PAIR_M_TOTAL = 1000          # realizations of the whole job
+PAIR_HEADROOM = 6 << 30      # device bytes left free next to the batch
 
 
-def c5_works(inputs):
+def pair_works(inputs):
     fine = inputs.WORKLOADS["jet5056"]
     coarse = inputs.JetWorkload("jet2528", fine.nx // 2, fine.ny // 2, fine.m, fine.t_final)
     return [coarse, fine]
@@ -335,7 +335,7 @@ def run_headline(args, torch, vlbm, inputs) -> int:
     between the levels."""
     import numpy as np
 
-    works = c5_works(inputs)
+    works = pair_works(inputs)
     coarse, fine = works
     t_final = fine.t_final
     levels = [(w.nx, w.ny, w.dx, w.y_min) for w in works]
@@ -370,7 +370,7 @@ def run_headline(args, torch, vlbm, inputs) -> int:
         return 0
 
     # the job's statistics: running accumulators and the sample stores of all M realizations
-    stores = [torch.zeros((C5_M_TOTAL, ncell), **dev) for _ in works]
+    stores = [torch.zeros((PAIR_M_TOTAL, ncell), **dev) for _ in works]
     acc = [torch.empty((3, 2, ncell), **dev) for _ in works]
     mean = [torch.empty((3, ncell), **dev) for _ in works]
     std = [torch.empty((3, ncell), **dev) for _ in works]
@@ -379,10 +379,10 @@ def run_headline(args, torch, vlbm, inputs) -> int:
     B = args.batch
     if B <= 0:
         free, _ = torch.cuda.mem_get_info()
-        B = int(max(1, min(64, (free - C5_HEADROOM) // per_real)))
-    slots = C5_M_TOTAL // B
+        B = int(max(1, min(64, (free - PAIR_HEADROOM) // per_real)))
+    slots = PAIR_M_TOTAL // B
     L = args.launches
-    progress(f"c5: batch of {B} realizations ({per_real / 1e9:.2f} GB each), {L} launches per step")
+    progress(f"jet5056pair: batch of {B} realizations ({per_real / 1e9:.2f} GB each), {L} launches per step")
 
     def variant(prec):
         params = vlbm.Params.jet(precision=prec)
@@ -466,8 +466,8 @@ def run_headline(args, torch, vlbm, inputs) -> int:
     e1 = torch.cuda.Event(enable_timing=True)
     e0.record(stream)
     for l in range(len(works)):
-        vlbm.vlbm_sort_samples(stores[l], ncell, C5_M_TOTAL, stream)
-    vlbm.vlbm_w1(stores[0], stores[1], ncell, C5_M_TOTAL, w1c, w1m, stream)
+        vlbm.vlbm_sort_samples(stores[l], ncell, PAIR_M_TOTAL, stream)
+    vlbm.vlbm_w1(stores[0], stores[1], ncell, PAIR_M_TOTAL, w1c, w1m, stream)
     e1.record(stream)
     e1.synchronize()
     final_ms = e0.elapsed_time(e1)
@@ -485,13 +485,13 @@ def run_headline(args, torch, vlbm, inputs) -> int:
         "scaling": "weak", "vs_baseline": None,
         "dtype": "f64" if head == "fp64" else "f32+f64",
         "data": "synthetic",
-        "config": {"workload": f"c5: Mach-2000 jet, the 5056x2528 level with its 2528x1264 partner on the same "
-                               f"seeds (domain [0,1]x[-0.25,0.25], t_final={t_final:g}), M={C5_M_TOTAL} "
+        "config": {"workload": f"jet5056pair: Mach-2000 jet, the 5056x2528 level with its 2528x1264 partner on the same "
+                               f"seeds (domain [0,1]x[-0.25,0.25], t_final={t_final:g}), M={PAIR_M_TOTAL} "
                                f"streamed in batches of {B}; one step = {L} step launches of both levels "
                                f"on one batch + its restriction to 2528x1264, Chan merge, scatter into the "
-                               f"M={C5_M_TOTAL} sample stores, per-cell sort and W1 between the levels, {head}",
+                               f"M={PAIR_M_TOTAL} sample stores, per-cell sort and W1 between the levels, {head}",
                    "precision": head, "levels": [[w.nx, w.ny] for w in works], "batch": B,
-                   "realizations_total": C5_M_TOTAL, "launches_per_step": L, "t_final": t_final,
+                   "realizations_total": PAIR_M_TOTAL, "launches_per_step": L, "t_final": t_final,
                    "seed": inputs.DEFAULT_SEED, "time_steps_reached": r0["steps"],
                    "t_reached": r0["t_reached"],
                    "node_updates_per_launch": B * lup_per_launch_per_real,
@@ -500,7 +500,7 @@ def run_headline(args, torch, vlbm, inputs) -> int:
                    "once_per_job_sort_and_w1_of_the_full_stores_ms": round(final_ms, 1)},
         "roofline": {"bound": "hbm", "achieved": round(r0["achieved"], 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(r0["achieved"] / HBM_PEAK_GBS, 4),
-                     "traffic": measured_traffic(head, "c5", B * lup_per_launch_per_real),
+                     "traffic": measured_traffic(head, "jet5056pair", B * lup_per_launch_per_real),
                      "kernel": "vlbm step kernel (both levels per launch)", "bytes_per_node_update": bpl,
                      "avg_launch_ms": round(r0["avg_launch_ms"], 4),
                      "device_copy_GBs": round(copy_gbs, 1),
@@ -515,7 +515,7 @@ def run_headline(args, torch, vlbm, inputs) -> int:
             "speedup_vs_fp64": round(rm["value"] / r0["value"], 4),
             "roofline": {"bound": "hbm", "achieved": round(rm["achieved"], 1), "peak": HBM_PEAK_GBS,
                          "unit": "GB/s", "frac": round(rm["achieved"] / HBM_PEAK_GBS, 4),
-                         "traffic": measured_traffic("mixed", "c5", B * lup_per_launch_per_real),
+                         "traffic": measured_traffic("mixed", "jet5056pair", B * lup_per_launch_per_real),
                          "bytes_per_node_update": BYTES_PER_LUP["mixed"],
                          "avg_launch_ms": round(rm["avg_launch_ms"], 4),
                          "frac_of_device_copy": round(rm["achieved"] / copy_gbs, 4)},
@@ -1031,7 +1031,7 @@ def run_w12(args, torch, vlbm) -> int:
     return 0
 
 
-def run_c5(args, torch, vlbm, inputs) -> int:
+def run_pair_full(args, torch, vlbm, inputs) -> int:
     """The largest level of the study and its half-resolution partner in one
     ensemble per batch (same seeds on both levels), batches streamed through
     HBM: the running statistics merge each batch (vlbm_ensemble_stats with
@@ -1044,7 +1044,7 @@ def run_c5(args, torch, vlbm, inputs) -> int:
     coarse = inputs.JetWorkload("jet2528", fine.nx // 2, fine.ny // 2, fine.m, fine.t_final)
     works = [coarse, fine]
     levels = [(w.nx, w.ny, w.dx, w.y_min) for w in works]
-    B, Mb = args.c5_batches, args.c5_batch_m
+    B, Mb = args.pair_batches, args.pair_batch_m
     M = B * Mb
     ncx, ncy = coarse.nx, coarse.ny
     ncell = ncx * ncy

@@ -41,15 +41,15 @@ def test_traffic_figure_is_tied_to_the_kernel_sources():
     only while the step kernel's sources hash to the value recorded with it;
     for another batch size it is scaled by the node updates per launch."""
     for prec in ("fp64", "mixed"):
-        path = os.path.join(ROOT, "profiles", f"traffic_step_c5_{prec}.json")
+        path = os.path.join(ROOT, "profiles", f"traffic_step_jet5056pair_{prec}.json")
         rec = json.load(open(path))
         assert rec["hashed_sources"] == list(rocprof_summary.STEP_KERNEL_SOURCES)
-        got = bench.measured_traffic(prec, "c5")
+        got = bench.measured_traffic(prec, "jet5056pair")
         if rec["kernel_source_hash"] == bench.kernel_source_hash():
             assert got == rec["bytes_per_launch"]
             # fetch + write, each scaled by the copy calibration
             assert got == pytest.approx(rec["fetch_bytes"] + rec["write_bytes"], rel=1e-12)
-            half = bench.measured_traffic(prec, "c5", rec["node_updates_per_launch"] / 2)
+            half = bench.measured_traffic(prec, "jet5056pair", rec["node_updates_per_launch"] / 2)
             assert half == pytest.approx(got / 2, rel=1e-12)
             # at least the algorithmic bytes, and not wildly more
             assert 1.0 <= got / rec["algorithmic_bytes_per_launch"] < 1.5
