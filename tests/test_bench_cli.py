@@ -108,3 +108,29 @@ def test_counter_summary_calibrates_by_the_last_copy(tmp_path):
     _counter_db(bare, "FETCH_SIZE", [(1, "vlbm::step_march_kernel<0>", 100.0)])
     with pytest.raises(RuntimeError):
         rocprof_summary.traffic(str(bare), str(write), "step_march_kernel")
+
+
+def test_committed_default_record_keeps_the_contract():
+    """The committed record of the default line has the benchmark's JSON
+    contract: the required keys, one GPU, a roofline whose fraction is the
+    achieved rate over the 8 TB/s peak and whose traffic is the counted bytes
+    of that workload's record, and the oracle baseline with its thread count
+    and sample."""
+    rec = json.load(open(os.path.join(ROOT, "profiles", "bench_jet5056pair_default.json")))
+    for key in ("metric", "value", "unit", "n_gpus", "steps", "warmup", "ms_per_step", "higher_is_better",
+                "scaling", "vs_baseline", "dtype", "data", "config", "roofline", "cpu_baseline"):
+        assert key in rec, key
+    assert rec["n_gpus"] == 1 and rec["unit"] == "GLUPS" and rec["dtype"] == "f64" and rec["higher_is_better"]
+    assert rec["config"]["workload"].startswith("jet5056pair")
+    roof = rec["roofline"]
+    assert roof["bound"] == "hbm" and roof["peak"] == bench.HBM_PEAK_GBS and roof["unit"] == "GB/s"
+    assert roof["frac"] == pytest.approx(roof["achieved"] / roof["peak"], abs=1e-4)
+    assert 0.6 <= roof["frac"] < 1.0
+    traffic = json.load(open(os.path.join(ROOT, "profiles", "traffic_step_jet5056pair_fp64.json")))
+    assert roof["traffic"] == pytest.approx(traffic["bytes_per_launch"], rel=1e-12)
+    cpu = rec["cpu_baseline"]
+    assert cpu["kind"] == "oracle" and cpu["unit"] == "GLUPS" and cpu["cores"] >= 1 and cpu["sample"]
+    assert 0.0 < cpu["value"] < rec["value"]
+    mixed = rec["mixed"]
+    assert mixed["roofline"]["bytes_per_node_update"] == bench.BYTES_PER_LUP["mixed"]
+    assert mixed["speedup_vs_fp64"] == pytest.approx(mixed["value"] / rec["value"], rel=1e-3)
