@@ -173,6 +173,7 @@ def built_oracle():
     oracle.build(force=False)
 
 
+@pytest.mark.slow
 @pytest.mark.parametrize("kind", ["scheme (C)", "statistics (Python)"])
 def test_every_planted_slip_fails_a_pin(kind, built_oracle):
     cases, fn = (C_SLIPS, _c_case) if kind.startswith("scheme") else (PY_SLIPS, _py_case)
