@@ -288,6 +288,8 @@ def mixed_error_study(torch, vlbm, inputs, w, fracs, chunk):
         vlbm.vlbm_ensemble_stats(ens.h, 0, r_w1, sacc, 0, smp, 0)
         vlbm.vlbm_sort_samples(smp, ncell_w1, R)
         ens.close()
+        progress(f"mixed-error study: {precision} ensemble (first seed {first_seed}, perturbation {ulp}) "
+                 f"at t={t_end:g}")
         return {"mean": mean, "std": std, "sorted": smp, "steps": [int(s.min()), int(s.max())]}
 
     out = []
